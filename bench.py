@@ -1,0 +1,170 @@
+"""Benchmark of the fused D3Q19 + D3Q7 thermal pseudopotential LB step.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                    [--storage f32|f64] [--tile TXxTY] [--chunk CZ] [--no-cpu-baseline]
+
+One step = one fused time step of the whole grid (both lattices, streaming and
+boundary rules) on synthetic seeded input already resident in HBM.  Prints one
+JSON line: MLUPS (million lattice-node updates per second), the HBM roofline
+of the step kernel and the FP64 oracle timed on the host as a CPU baseline.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS (D3Q19+D3Q7 fused step) + % HBM peak, FP16-store vs FP32 at stated error"
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per lattice update: 19 + 7 populations and the phi_s
+# history, each read once and written once.
+BYTES_PER_LUP = {"f32": 54 * 4, "f64": 54 * 8}
+KERNEL_SOURCES = ["paper_2201_06039_amd/csrc/lbm_kernels.hpp", "paper_2201_06039_amd/csrc/lbm_api.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_evaporation_128_traffic.json")
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, storage, launch):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source with the same workload and launch."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash() or t.get("workload") != workload or t.get("storage") != storage:
+        return None
+    if t.get("launch") != [launch["tile_x"], launch["tile_y"], launch["chunk_z"]]:
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, fields, seconds=15.0):
+    """The FP64 oracle on the host cores, on the same workload, for a bounded
+    number of steps sized to take about `seconds`."""
+    from oracle import sim
+    s = sim.Sim(**w["params"])
+    s.init_fields(*fields)
+    t0 = time.perf_counter()
+    s.step(1)
+    t1 = time.perf_counter()
+    per = max(t1 - t0, 1e-3)
+    n = max(1, int(seconds / per) - 1)
+    t0 = time.perf_counter()
+    s.step(n)
+    t1 = time.perf_counter()
+    nn = s.nn
+    s.close()
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(nn * n / (t1 - t0) / 1e6, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{n} steps of the full {w['params']['nx']}x{w['params']['ny']}x{w['params']['nz']} grid "
+                      f"after 1 untimed step, FP64 C + OpenMP"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="evaporation_128")
+    ap.add_argument("--storage", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--tile", default=None, help="TXxTY, e.g. 64x4")
+    ap.add_argument("--chunk", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
+                    help="only run 20 plain device-to-device copies of MB megabytes (to calibrate the "
+                         "FETCH_SIZE/WRITE_SIZE counters against a kernel of known traffic) and exit")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(20):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "calls": 20}))
+        return
+
+    from paper_2201_06039_amd import lbm, workloads as W
+
+    w = W.load(args.workload)
+    fields = W.fields(w)
+    p = w["params"]
+    nn = p["nx"] * p["ny"] * p["nz"]
+
+    lat = lbm.Lattice(p, storage=args.storage, device="cuda:0")
+    if args.tile or args.chunk:
+        cur = lat.launch()
+        tx, ty = (int(v) for v in args.tile.split("x")) if args.tile else (cur["tile_x"], cur["tile_y"])
+        lat.set_launch(tx, ty, args.chunk or cur["chunk_z"])
+    launch = lat.launch()
+    lat.init_fields(*fields)
+    print(f"# workload {args.workload} {p['nx']}x{p['ny']}x{p['nz']} storage {args.storage} launch {launch}",
+          file=sys.stderr, flush=True)
+
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    stream = lat.stream
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    lat.step(args.steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    # any instability during the timed steps fails the run
+    rho, ux, uy, uz, T = lat.rho_u_T()
+
+    sec = ms / 1e3
+    mlups = nn * args.steps / sec / 1e6
+    launches = lat.launches_per_step()
+    avg_launch_s = sec / args.steps  # the step kernel is the only launch per step when launches == 1
+    bytes_alg = BYTES_PER_LUP[args.storage] * nn
+    achieved = bytes_alg / avg_launch_s / 1e9
+    traffic = measured_traffic(args.workload, args.storage, launch)
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic",
+        "config": {"workload": args.workload, "grid": [p["nx"], p["ny"], p["nz"]], "storage": args.storage,
+                   "tile": [launch["tile_x"], launch["tile_y"]], "chunk_z": launch["chunk_z"],
+                   "workgroups": launch["workgroups"], "launches_per_step": launches},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "k_step", "bytes_per_lup": BYTES_PER_LUP[args.storage]},
+    }
+    lat.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, fields)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

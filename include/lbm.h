@@ -1,0 +1,152 @@
+/*
+ * liblbm -- C-ABI of the MI355X (gfx950) implementation of the fused time step
+ * of the improved 3D thermal multiphase lattice Boltzmann model of Li, Yu &
+ * Luo, "Improved three-dimensional thermal multiphase lattice Boltzmann model
+ * for liquid-vapor phase change" (arXiv:2201.06039):
+ *
+ *   - D3Q19 MRT pseudopotential lattice for density and velocity
+ *     (Sec. II, Eqs. (1)-(10)) with the Peng-Robinson EOS (Sec. IV A, Eq. (49));
+ *   - D3Q7 MRT lattice for temperature (Sec. III C, Eqs. (37)-(43)) whose
+ *     source phi_s (Sec. III A, Eq. (18)) uses the local temperature gradient
+ *     of Eq. (45) and the local velocity divergence of Eq. (48);
+ *   - halfway bounce-back (Eq. (50)) and anti-bounce-back (Eq. (51)) at a
+ *     bottom wall, an open top, and buoyancy F_b = (rho - rho_ave) g (Sec. IV C).
+ *
+ * Conventions shared by every call:
+ *   - Lattice units: delta_t = delta_x = c = 1.
+ *   - Node index i = x + nx * (y + ny * z); host field arrays are double
+ *     precision, structure of arrays, length nx*ny*nz, owned by the caller.
+ *     The library copies them and never keeps a host pointer.
+ *   - Device memory: the caller allocates one arena of lbm_arena_bytes() bytes
+ *     (for example a torch.uint8 CUDA tensor) and keeps it alive until
+ *     lbm_destroy().  The library never allocates device memory itself.
+ *   - All device work is enqueued on the stream passed to lbm_create()
+ *     (a hipStream_t; NULL means the default stream).  Calls that return host
+ *     data synchronise that stream; lbm_step() does not.
+ *   - A handle is not thread-safe.
+ *   - Every int-returning call returns an LBM_* status below.
+ *     lbm_strerror() gives a static description.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define LBM_OK 0
+#define LBM_EINVAL (-1)    /* invalid argument or parameter                    */
+#define LBM_ENOMEM (-2)    /* arena too small                                  */
+#define LBM_EHIP (-3)      /* HIP runtime error                                */
+#define LBM_EUNSTABLE (-4) /* a step produced rho <= 0, psi^2 < 0 or NaN       */
+#define LBM_ESTATE (-5)    /* call out of order (e.g. step before init)        */
+
+/* Boundary in z (x and y are always periodic). */
+#define LBM_BC_PERIODIC 0
+/* Halfway bounce-back wall below z = 0 (Eq. (50)) with anti-bounce-back
+ * Dirichlet temperature (Eq. (51)); open top at z = nz-1 whose unknown f are
+ * copied from the layer below and whose g obey Eq. (51) with T_top. */
+#define LBM_BC_WALL_BOTTOM_OPEN_TOP 1
+
+/* Thermal conductivity mode of Eq. (17): chi = lambda/(rho c_V). */
+#define LBM_KAPPA_CONST_LAMBDA 0 /* kappa is lambda; chi varies with rho per node */
+#define LBM_KAPPA_CONST_CHI 1    /* kappa is chi itself                           */
+
+/* Storage precision of the populations (arithmetic follows it: F32 storage
+ * computes in FP32, F64 storage computes in FP64). */
+#define LBM_STORE_F32 0
+#define LBM_STORE_F64 1
+
+/* Problem statement.  Field names are the paper's symbols. */
+typedef struct lbm_params {
+    int nx, ny, nz;          /* grid; nx, ny, nz >= 1 (nz >= 3 with walls)      */
+    int bc_z;                /* LBM_BC_*                                       */
+    double a, b, R;          /* Peng-Robinson constants, Eq. (49)              */
+    double acentric;         /* acentric factor omega of Eq. (49)              */
+    double G;                /* interaction strength of Eqs. (7)-(8), != 0     */
+    double sigma;            /* constant of the S_4 term of Eq. (9)            */
+    double tau_e, tau_v, tau_q, tau_pi; /* relaxation times of Eq. (6), > 1/2  */
+    double cV;               /* specific heat at constant volume, > 0          */
+    double d;                /* D3Q7 weights w0 = 1-d, w1..6 = d/6, 0 < d < 1  */
+    int kappa_mode;          /* LBM_KAPPA_*                                    */
+    double kappa;            /* lambda or chi, > 0                             */
+    double vs_q, vs_pi;      /* varsigma_q, varsigma_pi of Eq. (43), > 1/2      */
+    double g[3];             /* gravity in F_b = (rho - rho_ave) g             */
+    double T_wall_patch;     /* wall temperature inside the heated disc        */
+    double T_wall;           /* wall temperature outside it                    */
+    double patch_radius;     /* disc radius, centred at ((nx-1)/2, (ny-1)/2)   */
+    double T_top;            /* Dirichlet temperature of the open top          */
+    int thermal;             /* 1: temperature lattice evolves; 0: held fixed  */
+    int storage;             /* LBM_STORE_*                                    */
+} lbm_params;
+
+typedef struct lbm_handle lbm_handle;
+
+/* Device bytes the arena must hold for these parameters (0 if invalid).
+ * Layout: two copies of the 19 + 7 population planes (ping-pong), the
+ * phi_s history plane, six FP64 staging planes for init and readout, block
+ * partial sums and a few scalars, each region 256-byte aligned. */
+size_t lbm_arena_bytes(const lbm_params *p);
+
+/* Validate p, derive the constants (T_c from a, b, R as in Sec. IV A; c_sT^2 =
+ * d/3), carve the caller-owned arena and bind the HIP stream.
+ * EINVAL: bad parameter or NULL pointer; ENOMEM: arena_bytes too small or
+ * dev_arena not 256-byte aligned.  On success *out owns host memory only. */
+int lbm_create(const lbm_params *p, void *dev_arena, size_t arena_bytes, void *hip_stream, lbm_handle **out);
+
+/* Initial state (t = 0): f = M^-1 m_eq(rho, u) with Eq. (5), g = w T
+ * (Sec. III C), phi_s(t - dt) = 0; rho_ave of the buoyancy is the initial mean.
+ * EINVAL if rho <= 0, T <= 0 or psi^2 < 0 (Eq. (8)) at any node, or a NULL
+ * pointer.  Synchronises the stream. */
+int lbm_init_fields(lbm_handle *h, const double *rho, const double *ux, const double *uy, const double *uz,
+                    const double *T);
+
+/* Enqueue n >= 0 fused time steps (Eq. (1)-(10) collide + stream of f,
+ * Eq. (37)-(45), (48), (18), (23)-(24) of g) without blocking.  Step t uses the
+ * mean density at t - 1 in F_b.  ESTATE before lbm_init_fields. */
+int lbm_step(lbm_handle *h, int n);
+
+/* rho (Eq. (10)), u = (sum e f + F/2)/rho with the total force F (Eq. (10)),
+ * and T (Eq. (20)) at the current time, as FP64 host arrays of nx*ny*nz.
+ * Synchronises the stream; returns EUNSTABLE if any step since the last
+ * check saw rho <= 0, psi^2 < 0 or NaN (the arrays are still written). */
+int lbm_get_rho_u_T(lbm_handle *h, double *rho, double *ux, double *uy, double *uz, double *T);
+
+/* FP64 sums of rho and T over the grid.  Synchronises; may return EUNSTABLE. */
+int lbm_reduce(lbm_handle *h, double *mass, double *energy);
+
+/* Size of the raw checkpoint: header, f, g, phi_s history, rho_ave. */
+size_t lbm_state_bytes(const lbm_handle *h);
+
+/* Copy the raw state to/from a host buffer of lbm_state_bytes() bytes.
+ * Restoring and stepping reproduces the uninterrupted run bit for bit.
+ * EINVAL on a size, header or grid mismatch.  Both synchronise. */
+int lbm_get_state(lbm_handle *h, void *host_buf, size_t bytes);
+int lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes);
+
+/* Launch shape of the fused step kernel: an x-y tile of tile_x * tile_y
+ * nodes per workgroup marching over chunk_z planes.  Supported tiles:
+ * 64x4, 32x8, 64x8, 32x16, 128x4 (FP64 storage: 64x4 and 32x8 only);
+ * chunk_z >= 1 (values above nz are clamped to nz).  EINVAL otherwise.
+ * The result of a step does not depend on the launch shape. */
+int lbm_set_launch(lbm_handle *h, int tile_x, int tile_y, int chunk_z);
+int lbm_get_launch(const lbm_handle *h, int *tile_x, int *tile_y, int *chunk_z, int *workgroups);
+
+/* Number of kernel launches lbm_step() enqueues per time step (1, or 2 when
+ * gravity needs the rho_ave reduction). */
+int lbm_launches_per_step(const lbm_handle *h);
+
+/* Release host resources; the arena stays with the caller.  NULL-safe. */
+void lbm_destroy(lbm_handle *h);
+
+/* Static description of a status code. */
+const char *lbm_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,714 @@
+// Device code of liblbm for gfx950 (MI355X): the fused D3Q19 + D3Q7 time step
+// of Li, Yu & Luo (arXiv:2201.06039) and its helper kernels.
+//
+// State layout in HBM (structure of arrays, x fastest):
+//   f[alpha][z][y][x], alpha = 0..18   post-streaming D3Q19 populations at t
+//   g[alpha][z][y][x], alpha = 0..6    post-streaming D3Q7 populations at t
+//   phi[z][y][x]                       phi_s(x, t - dt), Eq. (23) history
+// Two copies of f and g ping-pong between steps (push streaming: a node
+// reads its own populations and writes the post-collision values to its
+// neighbours in the other copy).
+//
+// The fused step kernel assigns each workgroup an x-y tile of TX*TY nodes and
+// a chunk of z planes.  It marches up the chunk: for plane z+1 it computes
+// rho, T and psi of the tile plus a one-node halo into a 4-plane LDS ring, so
+// the 18-neighbour force of Eq. (7) and the density gradient at plane z read
+// same-time-level values from LDS.  Halo nodes are recomputed from their own
+// populations (an extra read served mostly by L2), which keeps the whole step
+// in one launch with 27 reads and 27 writes of state per node.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// Sec. II, Eq. (2): D3Q19 velocity components, alpha = 0..18.
+constexpr int kE19X[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int kE19Y[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int kE19Z[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+// Sec. III B, Eq. (21): D3Q7 velocity components.
+constexpr int kE7X[7] = {0, 1, -1, 0, 0, 0, 0};
+constexpr int kE7Y[7] = {0, 0, 0, 1, -1, 0, 0};
+constexpr int kE7Z[7] = {0, 0, 0, 0, 0, 1, -1};
+
+__host__ __device__ constexpr int opposite(int a) { return a == 0 ? 0 : ((a & 1) ? a + 1 : a - 1); }
+
+template <typename C>
+struct Num;
+template <>
+struct Num<float> {
+    __device__ static float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    __device__ static float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+};
+template <>
+struct Num<double> {
+    __device__ static double rcp(double x) { return 1.0 / x; }
+    __device__ static double sqrt(double x) { return ::sqrt(x); }
+};
+
+// Constants of the model in the compute type, derived on the host.
+template <typename C>
+struct Phys {
+    C a, b, R;            // Eq. (49)
+    C kap;                // 0.37464 + 1.54226 w - 0.26992 w^2
+    C inv_Tc;             // 1/T_c, T_c = (0.0778/0.45724) a/(b R)
+    C two_over_Gc2;       // psi^2 = 2 (p - rho c_s^2)/(G c^2), Eq. (8)
+    C negG;               // F_m = -G psi sum(...), Eq. (7)
+    C sig6;               // 6 sigma/(tau_e - 1/2), Eq. (9)
+    C lam_e, lam_v, lam_q, lam_pi;  // Eq. (6)
+    C divu_a, divu_b;     // Eq. (48): 1/tau_e and 1 - 1/(2 tau_e)
+    C cV, inv_cV;
+    C wT0, wT1;           // D3Q7 weights
+    C csT2, inv_csT2, d;  // c_sT^2 = d/3
+    C kappa;              // lambda or chi
+    C gam_q, gam_pi;      // 1/varsigma_q, 1/varsigma_pi
+    C gx, gy, gz;         // gravity
+    int kappa_mode;       // 0: constant lambda, 1: constant chi
+    int thermal;          // temperature lattice evolves
+    int attract;          // a != 0
+    int gravity;          // g != 0
+    double T_patch, T_wall, patch_r2, T_top, cx, cy;  // walls (decisions in FP64)
+};
+
+// psi^2 of Eq. (8) with the Peng-Robinson pressure of Eq. (49).  rho, T and
+// psi of a node are evaluated in several inlined copies (its own tile and the
+// halo of its neighbours' tiles); contraction into FMA is off here so that
+// every copy rounds identically and the result never depends on the tiling.
+template <typename C>
+__device__ __forceinline__ C psi_squared(const Phys<C> &P, C rho, C T) {
+#pragma clang fp contract(off)
+    C attraction = C(0);
+    if (P.attract) {
+        const C root = C(1) + P.kap * (C(1) - Num<C>::sqrt(T * P.inv_Tc));
+        attraction = P.a * root * root * rho * rho * Num<C>::rcp(C(1) + C(2) * P.b * rho - P.b * P.b * rho * rho);
+    }
+    const C p = rho * P.R * T * Num<C>::rcp(C(1) - P.b * rho) - attraction;
+    return P.two_over_Gc2 * (p - rho * C(1.0 / 3.0));
+}
+
+template <typename C>
+__device__ __forceinline__ C sum19(const C *f) {
+    return f[0] + (((f[1] + f[2]) + (f[3] + f[4])) + (f[5] + f[6])) +
+           (((f[7] + f[8]) + (f[9] + f[10])) + ((f[11] + f[12]) + (f[13] + f[14])) +
+            ((f[15] + f[16]) + (f[17] + f[18])));
+}
+
+template <typename C>
+__device__ __forceinline__ C sum7(const C *g) {
+    return g[0] + ((g[1] + g[2]) + (g[3] + g[4]) + (g[5] + g[6]));
+}
+
+// m = M f for the raw monomial basis (1, e, |e|^2, 2ex^2-ey^2-ez^2, ey^2-ez^2,
+// exey, exez, eyez, ex^2ey, exey^2, ex^2ez, exez^2, ey^2ez, eyez^2, ex^2ey^2,
+// ex^2ez^2, ey^2ez^2), evaluated with pair sums and differences.  m[0] is not
+// formed (it is rho).  With `rho` given, m[4], m[16..18] are returned as
+// deviations from the rest equilibrium w rho (m4 - rho = q - f0 with q the
+// sum of the twelve diagonal populations, m16..18 - rho/9), which avoids
+// differences of O(rho) numbers.
+template <typename C, bool DEV = false>
+__device__ __forceinline__ void moments19(const C *f, C *m, C rho = C(0)) {
+    const C a1 = f[1] + f[2], d1 = f[1] - f[2];
+    const C a3 = f[3] + f[4], d3 = f[3] - f[4];
+    const C a5 = f[5] + f[6], d5 = f[5] - f[6];
+    const C s78 = f[7] + f[8], d78 = f[7] - f[8], s910 = f[9] + f[10], d910 = f[9] - f[10];
+    const C s1112 = f[11] + f[12], d1112 = f[11] - f[12], s1314 = f[13] + f[14], d1314 = f[13] - f[14];
+    const C s1516 = f[15] + f[16], d1516 = f[15] - f[16], s1718 = f[17] + f[18], d1718 = f[17] - f[18];
+    m[16] = s78 + s910;
+    m[17] = s1112 + s1314;
+    m[18] = s1516 + s1718;
+    m[7] = s78 - s910;
+    m[8] = s1112 - s1314;
+    m[9] = s1516 - s1718;
+    m[10] = d78 - d910;
+    m[11] = d78 + d910;
+    m[12] = d1112 - d1314;
+    m[13] = d1112 + d1314;
+    m[14] = d1516 - d1718;
+    m[15] = d1516 + d1718;
+    m[1] = d1 + m[11] + m[13];
+    m[2] = d3 + m[10] + m[15];
+    m[3] = d5 + m[12] + m[14];
+    const C A = a1 + a3 + a5;
+    m[5] = C(2) * a1 - a3 - a5 + m[16] + m[17] - C(2) * m[18];
+    m[6] = a3 - a5 + m[16] - m[17];
+    if (DEV) {
+        m[4] = (m[16] + m[17] + m[18]) - f[0];
+        const C r9 = rho * C(1.0 / 9.0);
+        m[16] -= r9;
+        m[17] -= r9;
+        m[18] -= r9;
+    } else {
+        m[4] = A + C(2) * (m[16] + m[17] + m[18]);
+    }
+}
+
+// f = M^-1 m, the exact inverse of moments19 (m[0] = rho included).
+template <typename C>
+__device__ __forceinline__ void populations19(const C *m, C *f) {
+    const C q = m[16] + m[17] + m[18];
+    const C A = m[4] - C(2) * q;
+    const C a1 = (m[5] + A - m[16] - m[17] + C(2) * m[18]) * C(1.0 / 3.0);
+    const C b35 = m[6] - m[16] + m[17];
+    const C r35 = A - a1;
+    const C a3 = C(0.5) * (r35 + b35), a5 = C(0.5) * (r35 - b35);
+    const C d1 = m[1] - m[11] - m[13];
+    const C d3 = m[2] - m[10] - m[15];
+    const C d5 = m[3] - m[12] - m[14];
+    f[0] = m[0] - A - q;
+    f[1] = C(0.5) * (a1 + d1);
+    f[2] = C(0.5) * (a1 - d1);
+    f[3] = C(0.5) * (a3 + d3);
+    f[4] = C(0.5) * (a3 - d3);
+    f[5] = C(0.5) * (a5 + d5);
+    f[6] = C(0.5) * (a5 - d5);
+    const C s78 = C(0.5) * (m[16] + m[7]), s910 = C(0.5) * (m[16] - m[7]);
+    const C d78 = C(0.5) * (m[10] + m[11]), d910 = C(0.5) * (m[11] - m[10]);
+    f[7] = C(0.5) * (s78 + d78);
+    f[8] = C(0.5) * (s78 - d78);
+    f[9] = C(0.5) * (s910 + d910);
+    f[10] = C(0.5) * (s910 - d910);
+    const C s1112 = C(0.5) * (m[17] + m[8]), s1314 = C(0.5) * (m[17] - m[8]);
+    const C d1112 = C(0.5) * (m[12] + m[13]), d1314 = C(0.5) * (m[13] - m[12]);
+    f[11] = C(0.5) * (s1112 + d1112);
+    f[12] = C(0.5) * (s1112 - d1112);
+    f[13] = C(0.5) * (s1314 + d1314);
+    f[14] = C(0.5) * (s1314 - d1314);
+    const C s1516 = C(0.5) * (m[18] + m[9]), s1718 = C(0.5) * (m[18] - m[9]);
+    const C d1516 = C(0.5) * (m[14] + m[15]), d1718 = C(0.5) * (m[15] - m[14]);
+    f[15] = C(0.5) * (s1516 + d1516);
+    f[16] = C(0.5) * (s1516 - d1516);
+    f[17] = C(0.5) * (s1718 + d1718);
+    f[18] = C(0.5) * (s1718 - d1718);
+}
+
+// Eq. (5): equilibrium moments 4..18 (0..3 are rho and rho u).
+template <typename C>
+__device__ __forceinline__ void equilibrium19(C rho, C ux, C uy, C uz, C *meq) {
+    constexpr C cs2 = C(1.0 / 3.0);
+    const C ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
+    const C usq = ux2 + uy2 + uz2;
+    const C varphi = rho * C(1.0 / 9.0) * (C(1) - C(1.5) * usq);
+    meq[0] = rho;
+    meq[1] = rho * ux;
+    meq[2] = rho * uy;
+    meq[3] = rho * uz;
+    meq[4] = rho + rho * usq;
+    meq[5] = rho * (C(2) * ux2 - uy2 - uz2);
+    meq[6] = rho * (uy2 - uz2);
+    meq[7] = rho * ux * uy;
+    meq[8] = rho * ux * uz;
+    meq[9] = rho * uy * uz;
+    meq[10] = rho * uy * (cs2 + ux2);
+    meq[11] = rho * ux * (cs2 + uy2);
+    meq[12] = rho * uz * (cs2 + ux2);
+    meq[13] = rho * ux * (cs2 + uz2);
+    meq[14] = rho * uz * (cs2 + uy2);
+    meq[15] = rho * uy * (cs2 + uz2);
+    meq[16] = varphi + rho * cs2 * (ux2 + uy2);
+    meq[17] = varphi + rho * cs2 * (ux2 + uz2);
+    meq[18] = varphi + rho * cs2 * (uy2 + uz2);
+}
+
+template <typename S, typename C>
+struct StepArgs {
+    const S *__restrict__ f_in;
+    S *__restrict__ f_out;
+    const S *__restrict__ g_in;
+    S *__restrict__ g_out;
+    C *__restrict__ phi;
+    const double *__restrict__ rho_ave;
+    double *__restrict__ partials;  // per-workgroup sum of rho (when gravity is on)
+    unsigned *__restrict__ status;
+    size_t stride;                  // elements between population planes
+    int nx, ny, nz;
+    int ntx, nty, cz;               // tiles in x, y; planes per chunk
+    Phys<C> P;
+};
+
+// Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b mod 8).  Give each XCD a contiguous range of logical tiles, so that
+// workgroups sharing halo rows share an L2.
+__device__ __forceinline__ int xcd_logical_block(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7, xcd = b & 7;
+    return xcd * q + (xcd < r ? xcd : r) + (b >> 3);
+}
+
+// Loads and stores at a 32-bit byte offset from a uniform base: the base stays
+// in SGPRs and the access uses the scalar-base + 32-bit vector-offset form, so
+// no 64-bit address arithmetic is spent per access.
+template <typename T>
+__device__ __forceinline__ T ldg(const T *base, unsigned boff) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + boff);
+}
+template <typename T>
+__device__ __forceinline__ void stg(T *base, unsigned boff, T v) {
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + boff) = v;
+}
+
+// a * b + c rounded once (the library is built without automatic contraction,
+// so every fused operation is one of these and the rounding is fixed).
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename S, typename C, int TX, int TY, bool WALLS>
+__global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<S, C> A) {
+    constexpr int NT = TX * TY, EX = TX + 2, EY = TY + 2, NE = EX * EY, NH = NE - NT;
+    static_assert(NH <= NT, "halo must not exceed the tile");
+    constexpr unsigned ES = sizeof(S);
+    __shared__ C s_psi[4][NE];
+    __shared__ C s_rho[4][NE];
+    __shared__ double s_red[NT / 64];
+
+    const Phys<C> &P = A.P;
+    const int nx = A.nx, ny = A.ny, nz = A.nz;
+    const unsigned plane = (unsigned)nx * (unsigned)ny;
+    const size_t st = A.stride;
+
+    const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int itx = logical % A.ntx;
+    const int rest = logical / A.ntx;
+    const int ity = rest % A.nty;
+    const int izc = rest / A.nty;
+    const int x0 = itx * TX, y0 = ity * TY, z0 = izc * A.cz;
+    const int zend = min(z0 + A.cz, nz);
+
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const int x = x0 + tx, y = y0 + ty;
+    const bool active = x < nx && y < ny;
+    const int xw = x % nx, yw = y % ny;
+    const int li = (ty + 1) * EX + (tx + 1);
+    const unsigned irow = (unsigned)yw * nx + xw;
+
+    // Halo position owned by this thread (tid < NH): the rows below and above
+    // the tile, then the columns left and right of it.
+    const bool has_halo = tid < NH;
+    unsigned hrow = 0;
+    int hli = 0;
+    if (has_halo) {
+        int ex, ey;
+        if (tid < EX) { ex = tid - 1; ey = -1; }
+        else if (tid < 2 * EX) { ex = tid - EX - 1; ey = TY; }
+        else if (tid < 2 * EX + TY) { ex = -1; ey = tid - 2 * EX; }
+        else { ex = TX; ey = tid - 2 * EX - TY; }
+        const int hx = ((x0 + ex) % nx + nx) % nx;
+        const int hy = ((y0 + ey) % ny + ny) % ny;
+        hrow = (unsigned)hy * nx + hx;
+        hli = (ey + 1) * EX + (ex + 1);
+    }
+
+    auto zmap = [&](int zp) -> int {
+        if (WALLS) return zp < 0 ? 0 : (zp > nz - 1 ? nz - 1 : zp);
+        int zz = zp % nz;
+        return zz < 0 ? zz + nz : zz;
+    };
+
+    // rho, T, psi of plane zp for the tile and its halo -> LDS slot.
+    auto moments_plane = [&](int zp, int slot, C *kf, C *kg, C &krho, C &kT, C &kpsi) {
+        const unsigned zoff = (unsigned)zmap(zp) * plane;
+        const unsigned ib = (zoff + irow) * ES;
+#pragma unroll
+        for (int a = 0; a < 19; ++a) kf[a] = (C)ldg(A.f_in + a * st, ib);
+#pragma unroll
+        for (int a = 0; a < 7; ++a) kg[a] = (C)ldg(A.g_in + a * st, ib);
+        C hf[19], hg[7];
+        if (has_halo) {
+            const unsigned hb = (zoff + hrow) * ES;
+#pragma unroll
+            for (int a = 0; a < 19; ++a) hf[a] = (C)ldg(A.f_in + a * st, hb);
+#pragma unroll
+            for (int a = 0; a < 7; ++a) hg[a] = (C)ldg(A.g_in + a * st, hb);
+        }
+        const C rho = sum19(kf), T = sum7(kg);
+        const C p2 = psi_squared(P, rho, T);
+        if (active && (!(rho > C(0)) || !(p2 >= C(0)))) atomicOr(A.status, 1u);
+        const C psi = Num<C>::sqrt(p2 > C(0) ? p2 : C(0));
+        s_psi[slot][li] = psi;
+        s_rho[slot][li] = rho;
+        krho = rho;
+        kT = T;
+        kpsi = psi;
+        if (has_halo) {
+            const C hr = sum19(hf), hT = sum7(hg);
+            const C hp2 = psi_squared(P, hr, hT);
+            s_psi[slot][hli] = Num<C>::sqrt(hp2 > C(0) ? hp2 : C(0));
+            s_rho[slot][hli] = hr;
+        }
+    };
+
+    // Streaming byte offsets inside a plane (periodic in x and y).
+    const int xm = xw == 0 ? nx - 1 : xw - 1, xp = xw == nx - 1 ? 0 : xw + 1;
+    const int ym = yw == 0 ? ny - 1 : yw - 1, yp = yw == ny - 1 ? 0 : yw + 1;
+    const unsigned Xo[3] = {(unsigned)xm * ES, (unsigned)xw * ES, (unsigned)xp * ES};
+    const unsigned Yo[3] = {(unsigned)ym * nx * ES, (unsigned)yw * nx * ES, (unsigned)yp * nx * ES};
+    C T_bottom = C(0);
+    if (WALLS) {
+        const double dx = xw - P.cx, dy = yw - P.cy;
+        T_bottom = (C)(dx * dx + dy * dy <= P.patch_r2 ? P.T_patch : P.T_wall);
+    }
+    const C rho_ave = (C)(*A.rho_ave);
+
+    C cf[19], cg[7], c_rho, c_T, c_psi;
+    C nf[19], ng[7], n_rho, n_T, n_psi;
+    {
+        C tf[19], tg[7], t0, t1, t2;
+        moments_plane(z0 - 1, 0, tf, tg, t0, t1, t2);
+    }
+    moments_plane(z0, 1, cf, cg, c_rho, c_T, c_psi);
+    double rho_sum = 0.0;
+
+    for (int z = z0; z < zend; ++z) {
+        const int s = z - z0 + 1;
+        moments_plane(z + 1, (s + 1) & 3, nf, ng, n_rho, n_T, n_psi);
+        __syncthreads();
+        if (active) {
+            const int sm = (s + 3) & 3, s0 = s & 3, sp = (s + 1) & 3;
+            // Eq. (7) and the isotropic gradient: omega(1) = 1/6, omega(2) = 1/12.
+#define NB(arr, sl, dx, dy) arr[sl][li + (dy) * EX + (dx)]
+#define STENCIL(arr, OX, OY, OZ)                                                                                    \
+    {                                                                                                               \
+        const C xy = NB(arr, s0, 1, 1) - NB(arr, s0, -1, -1), xmy = NB(arr, s0, 1, -1) - NB(arr, s0, -1, 1);        \
+        const C xz = NB(arr, sp, 1, 0) - NB(arr, sm, -1, 0), xmz = NB(arr, sm, 1, 0) - NB(arr, sp, -1, 0);          \
+        const C yz = NB(arr, sp, 0, 1) - NB(arr, sm, 0, -1), ymz = NB(arr, sm, 0, 1) - NB(arr, sp, 0, -1);          \
+        OX = fmad(C(1.0 / 6.0), NB(arr, s0, 1, 0) - NB(arr, s0, -1, 0), C(1.0 / 12.0) * ((xy + xmy) + (xz + xmz))); \
+        OY = fmad(C(1.0 / 6.0), NB(arr, s0, 0, 1) - NB(arr, s0, 0, -1), C(1.0 / 12.0) * ((xy - xmy) + (yz + ymz))); \
+        OZ = fmad(C(1.0 / 6.0), NB(arr, sp, 0, 0) - NB(arr, sm, 0, 0), C(1.0 / 12.0) * ((xz - xmz) + (yz - ymz))); \
+    }
+            C Spx, Spy, Spz, grx, gry, grz;
+            STENCIL(s_psi, Spx, Spy, Spz)
+            STENCIL(s_rho, grx, gry, grz)
+#undef STENCIL
+#undef NB
+            const C rho = c_rho, T = c_T, psi = c_psi;
+            const C inv_rho = Num<C>::rcp(rho);
+            const C gpsi = P.negG * psi;
+            const C fmx = gpsi * Spx, fmy = gpsi * Spy, fmz = gpsi * Spz;
+            C Fx = fmx, Fy = fmy, Fz = fmz;
+            if (P.gravity) {
+                const C drho = rho - rho_ave;
+                Fx = fmad(drho, P.gx, Fx);
+                Fy = fmad(drho, P.gy, Fy);
+                Fz = fmad(drho, P.gz, Fz);
+            }
+            // Moments as deviations from the rest equilibrium w rho: the rest
+            // part is conserved by the collision (Lambda_0 = 1, S_0 = 0, and
+            // m_eq(rho, 0) relaxes onto itself), so it is added back to f*
+            // at the end instead of being carried through O(rho) sums.
+            C m[19];
+            moments19<C, true>(cf, m, rho);
+            // Eq. (10)
+            const C ux = fmad(C(0.5), Fx, m[1]) * inv_rho;
+            const C uy = fmad(C(0.5), Fy, m[2]) * inv_rho;
+            const C uz = fmad(C(0.5), Fz, m[3]) * inv_rho;
+            // Eq. (5) for m5..m15, and the deviations from m_eq(rho, 0) of m4
+            // and m16..m18 (m4 - rho, m16..18 - rho/9).
+            constexpr C cs2 = C(1.0 / 3.0);
+            const C ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
+            const C rux = rho * ux, ruy = rho * uy, ruz = rho * uz;
+            const C r3 = rho * cs2;
+            const C rxx = rux * ux, ryy = ruy * uy, rzz = ruz * uz;  // rho u_i^2
+            const C r6 = C(0.5) * cs2 * (rxx + ryy + rzz);           // rho |u|^2 / 6
+            C meq[19];
+            meq[4] = rxx + ryy + rzz;
+            meq[5] = C(2) * rxx - ryy - rzz;
+            meq[6] = ryy - rzz;
+            meq[7] = rux * uy;
+            meq[8] = rux * uz;
+            meq[9] = ruy * uz;
+            meq[10] = fmad(rxx, uy, r3 * uy);
+            meq[11] = fmad(ryy, ux, r3 * ux);
+            meq[12] = fmad(rxx, uz, r3 * uz);
+            meq[13] = fmad(rzz, ux, r3 * ux);
+            meq[14] = fmad(ryy, uz, r3 * uz);
+            meq[15] = fmad(rzz, uy, r3 * uy);
+            meq[16] = fmad(cs2, rxx + ryy, -r6);
+            meq[17] = fmad(cs2, rxx + rzz, -r6);
+            meq[18] = fmad(cs2, ryy + rzz, -r6);
+            (void)ux2; (void)uy2; (void)uz2;
+            // Eq. (9)
+            const C xFx = ux * Fx, yFy = uy * Fy, zFz = uz * Fz;
+            const C Fu = xFx + yFy + zFz;
+            const C fm2 = fmad(fmx, fmx, fmad(fmy, fmy, fmz * fmz));
+            const C S4 = fmad(P.sig6 * fm2, Num<C>::rcp(psi * psi), C(2) * Fu);
+            // Eq. (3): m* = m + Lambda (m_eq - m) + (I - Lambda/2) S
+            C ms[19];
+            ms[0] = C(0);
+            ms[1] = m[1] + Fx;
+            ms[2] = m[2] + Fy;
+            ms[3] = m[3] + Fz;
+            ms[4] = fmad(P.lam_e, meq[4] - m[4], fmad(C(1) - C(0.5) * P.lam_e, S4, m[4]));
+            const C hv = C(1) - C(0.5) * P.lam_v;
+            ms[5] = fmad(P.lam_v, meq[5] - m[5], fmad(hv * C(2), C(2) * xFx - yFy - zFz, m[5]));
+            ms[6] = fmad(P.lam_v, meq[6] - m[6], fmad(hv * C(2), yFy - zFz, m[6]));
+            ms[7] = fmad(P.lam_v, meq[7] - m[7], fmad(hv, fmad(Fx, uy, Fy * ux), m[7]));
+            ms[8] = fmad(P.lam_v, meq[8] - m[8], fmad(hv, fmad(Fx, uz, Fz * ux), m[8]));
+            ms[9] = fmad(P.lam_v, meq[9] - m[9], fmad(hv, fmad(Fy, uz, Fz * uy), m[9]));
+            const C hq = (C(1) - C(0.5) * P.lam_q) * cs2;
+            ms[10] = fmad(P.lam_q, meq[10] - m[10], fmad(hq, Fy, m[10]));
+            ms[11] = fmad(P.lam_q, meq[11] - m[11], fmad(hq, Fx, m[11]));
+            ms[12] = fmad(P.lam_q, meq[12] - m[12], fmad(hq, Fz, m[12]));
+            ms[13] = fmad(P.lam_q, meq[13] - m[13], fmad(hq, Fx, m[13]));
+            ms[14] = fmad(P.lam_q, meq[14] - m[14], fmad(hq, Fz, m[14]));
+            ms[15] = fmad(P.lam_q, meq[15] - m[15], fmad(hq, Fy, m[15]));
+            const C hp = (C(1) - C(0.5) * P.lam_pi) * C(2) * cs2;
+            ms[16] = fmad(P.lam_pi, meq[16] - m[16], fmad(hp, xFx + yFy, m[16]));
+            ms[17] = fmad(P.lam_pi, meq[17] - m[17], fmad(hp, xFx + zFz, m[17]));
+            ms[18] = fmad(P.lam_pi, meq[18] - m[18], fmad(hp, yFy + zFz, m[18]));
+            C fs[19];
+            populations19(ms, fs);
+            {
+                // rest part w rho; r0 closes the sum exactly, since the
+                // rounded weights 1/3 + 6/18 + 12/36 do not add up to 1.
+                const C r1 = rho * C(1.0 / 18.0), r2 = rho * C(1.0 / 36.0);
+                const C r0 = rho - fmad(C(6), r1, C(12) * r2);
+                fs[0] += r0;
+#pragma unroll
+                for (int a = 1; a < 7; ++a) fs[a] += r1;
+#pragma unroll
+                for (int a = 7; a < 19; ++a) fs[a] += r2;
+            }
+
+            // ---- D3Q7 thermal lattice ----
+            C gp[7];
+            const unsigned own = (unsigned)z * plane + irow;
+            if (P.thermal) {
+                // Eq. (48): local velocity divergence (pre-collision m_4).
+                const C divu = fmad(P.divu_b, S4, -fmad(P.divu_a, m[4] - meq[4], C(2) * Fu)) * (C(1.5) * inv_rho);
+                // Eq. (38): n = N g
+                const C n1 = cg[1] - cg[2], n2 = cg[3] - cg[4], n3 = cg[5] - cg[6];
+                const C a12 = cg[1] + cg[2], a34 = cg[3] + cg[4], a56 = cg[5] + cg[6];
+                const C n5 = a12 - a34, n6 = a12 - a56;
+                const C chi = P.kappa_mode ? P.kappa : P.kappa * inv_rho * P.inv_cV;
+                const C inv_vsT = Num<C>::rcp(fmad(chi, P.inv_csT2, C(0.5)));
+                // Eq. (45): local temperature gradient.
+                const C kgr = -inv_vsT * P.inv_csT2;
+                const C dTx = kgr * n1, dTy = kgr * n2, dTz = kgr * n3;
+                // Eq. (18) with (dp/dT)_rho = rho R/(1 - b rho), constant c_V.
+                const C cr = chi * inv_rho;
+                const C adv = fmad(fmad(cr, grx, -ux), dTx, fmad(fmad(cr, gry, -uy), dTy, fmad(cr, grz, -uz) * dTz));
+                const C phis = fmad(-T * P.R * P.inv_cV, Num<C>::rcp(fmad(-P.b, rho, C(1))) * divu, adv);
+                // Eq. (39) with Eq. (42)-(43); n4 is carried as its deviation
+                // n4 - d T = (1 - d) T - g0 from the equilibrium.
+                const C keep = C(1) - inv_vsT;
+                const C s1 = n1 * keep, s2 = n2 * keep, s3 = n3 * keep;
+                const C s4 = fmad(P.wT0, T, -cg[0]) * (C(1) - P.gam_q);
+                const C s5 = n5 * (C(1) - P.gam_pi), s6 = n6 * (C(1) - P.gam_pi);
+                // Eqs. (23)-(24): Q = w (1.5 phi_s - 0.5 phi_s(t-1))
+                const unsigned ob = own * (unsigned)sizeof(C);
+                const C qs = fmad(C(1.5), phis, C(-0.5) * ldg(A.phi, ob));
+                const C Q0 = P.wT0 * qs, Q1 = P.wT1 * qs;
+                // Eq. (40)-(41): g+ = N^-1 n* + Q = w T + N^-1 (n* - n_eq) + Q
+                const C wT = P.wT1 * T;
+                const C c456 = (s4 + s5 + s6) * C(1.0 / 6.0);
+                const C c3 = (s4 - C(2) * s5 + s6) * C(1.0 / 6.0), c5 = (s4 + s5 - C(2) * s6) * C(1.0 / 6.0);
+                gp[0] = (T - C(6) * wT) - s4 + Q0;
+                gp[1] = wT + (fmad(C(0.5), s1, c456) + Q1);
+                gp[2] = wT + (fmad(C(-0.5), s1, c456) + Q1);
+                gp[3] = wT + (fmad(C(0.5), s2, c3) + Q1);
+                gp[4] = wT + (fmad(C(-0.5), s2, c3) + Q1);
+                gp[5] = wT + (fmad(C(0.5), s3, c5) + Q1);
+                gp[6] = wT + (fmad(C(-0.5), s3, c5) + Q1);
+                stg(A.phi, ob, phis);
+            }
+
+            // ---- streaming (push), Eq. (4) and Eq. (40) ----
+            const unsigned PB = plane * ES;
+            const unsigned Zc = (unsigned)z * PB;
+            unsigned Zo[3];
+            if (WALLS) {
+                Zo[0] = z > 0 ? Zc - PB : 0u;
+                Zo[1] = Zc;
+                Zo[2] = z < nz - 1 ? Zc + PB : 0u;
+            } else {
+                Zo[0] = (unsigned)(z == 0 ? nz - 1 : z - 1) * PB;
+                Zo[1] = Zc;
+                Zo[2] = (unsigned)(z == nz - 1 ? 0 : z + 1) * PB;
+            }
+            const unsigned ownb = own * ES;
+#pragma unroll
+            for (int a = 0; a < 19; ++a) {
+                const int ex = kE19X[a], ey = kE19Y[a], ez = kE19Z[a];
+                const unsigned inrow = Yo[ey + 1] + Xo[ex + 1];
+                if (WALLS) {
+                    if (ez < 0 && z == 0) {  // Eq. (50): halfway bounce-back
+                        stg(A.f_out + opposite(a) * st, ownb, (S)fs[a]);
+                        continue;
+                    }
+                    if (ez > 0 && z == nz - 1) continue;  // leaves through the open top
+                    if (ez < 0 && z == nz - 1)             // open top: unknown f copied from below
+                        stg(A.f_out + a * st, Zc + inrow, (S)fs[a]);
+                }
+                stg(A.f_out + a * st, Zo[ez + 1] + inrow, (S)fs[a]);
+            }
+            if (P.thermal) {
+#pragma unroll
+                for (int a = 0; a < 7; ++a) {
+                    const int ex = kE7X[a], ey = kE7Y[a], ez = kE7Z[a];
+                    if (WALLS) {
+                        if (ez < 0 && z == 0) {  // Eq. (51) at the wall
+                            stg(A.g_out + opposite(a) * st, ownb, (S)fmad(C(2) * P.wT1, T_bottom, -gp[a]));
+                            continue;
+                        }
+                        if (ez > 0 && z == nz - 1) {  // Eq. (51) with T_top
+                            stg(A.g_out + opposite(a) * st, ownb, (S)fmad(C(2) * P.wT1, (C)P.T_top, -gp[a]));
+                            continue;
+                        }
+                    }
+                    stg(A.g_out + a * st, Zo[ez + 1] + Yo[ey + 1] + Xo[ex + 1], (S)gp[a]);
+                }
+            } else {
+#pragma unroll
+                for (int a = 0; a < 7; ++a) stg(A.g_out + a * st, ownb, (S)cg[a]);
+            }
+            if (P.gravity) rho_sum += (double)rho;
+        }
+#pragma unroll
+        for (int a = 0; a < 19; ++a) cf[a] = nf[a];
+#pragma unroll
+        for (int a = 0; a < 7; ++a) cg[a] = ng[a];
+        c_rho = n_rho;
+        c_T = n_T;
+        c_psi = n_psi;
+    }
+
+    if (P.gravity) {
+        // Deterministic per-workgroup partial sum of rho(t) for rho_ave.
+        for (int o = 32; o > 0; o >>= 1) rho_sum += __shfl_xor(rho_sum, o, 64);
+        if ((tid & 63) == 0) s_red[tid >> 6] = rho_sum;
+        __syncthreads();
+        if (tid == 0) {
+            double acc = 0.0;
+            for (int w = 0; w < NT / 64; ++w) acc += s_red[w];
+            A.partials[blockIdx.x] = acc;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Helper kernels (one thread per node; not on the per-step path).
+// ---------------------------------------------------------------------------
+
+// Initial populations from FP64 fields: f = M^-1 m_eq(rho, u), g = w T,
+// phi = 0; sets status bit 2 where rho <= 0, T <= 0 or psi^2 < 0.
+template <typename S, typename C>
+__global__ void __launch_bounds__(256) k_init(const double *__restrict__ stage, size_t nn, S *__restrict__ f,
+                                              S *__restrict__ g, C *__restrict__ phi, size_t st, Phys<double> P,
+                                              unsigned *__restrict__ status) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nn) return;
+    const double rho = stage[i], ux = stage[nn + i], uy = stage[2 * nn + i], uz = stage[3 * nn + i],
+                 T = stage[4 * nn + i];
+    const double p2 = T > 0.0 ? psi_squared(P, rho, T) : -1.0;
+    if (!(rho > 0.0) || !(T > 0.0) || !(p2 >= 0.0)) atomicOr(status, 2u);
+    double meq[19], fl[19];
+    equilibrium19(rho, ux, uy, uz, meq);
+    populations19(meq, fl);
+#pragma unroll
+    for (int a = 0; a < 19; ++a) f[a * st + i] = (S)fl[a];
+    g[i] = (S)(P.wT0 * T);
+#pragma unroll
+    for (int a = 1; a < 7; ++a) g[a * st + i] = (S)(P.wT1 * T);
+    phi[i] = C(0);
+}
+
+// Per-node rho, T (and psi) in FP64 into the staging planes 0, 4, 5.
+template <typename S>
+__global__ void __launch_bounds__(256) k_macro(const S *__restrict__ f, const S *__restrict__ g, size_t st, size_t nn,
+                                               Phys<double> P, double *__restrict__ stage) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nn) return;
+    double fl[19], gl[7];
+#pragma unroll
+    for (int a = 0; a < 19; ++a) fl[a] = (double)f[a * st + i];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) gl[a] = (double)g[a * st + i];
+    const double rho = sum19(fl), T = sum7(gl);
+    const double p2 = psi_squared(P, rho, T);
+    stage[i] = rho;
+    stage[4 * nn + i] = T;
+    stage[5 * nn + i] = ::sqrt(p2 > 0.0 ? p2 : 0.0);
+}
+
+// u of Eq. (10) with the total force, in FP64, into staging planes 1..3.
+template <typename S>
+__global__ void __launch_bounds__(256) k_velocity(const S *__restrict__ f, size_t st, int nx, int ny, int nz,
+                                                  int walls, Phys<double> P, const double *__restrict__ rho_ave,
+                                                  double *__restrict__ stage) {
+    const size_t nn = (size_t)nx * ny * nz;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nn) return;
+    const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((size_t)nx * ny));
+    const double *psi = stage + 5 * nn;
+    double Sp[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 1; a < 19; ++a) {
+        const int xn = (x + kE19X[a] + nx) % nx, yn = (y + kE19Y[a] + ny) % ny;
+        int zn = z + kE19Z[a];
+        if (walls) zn = zn < 0 ? 0 : (zn > nz - 1 ? nz - 1 : zn);
+        else zn = (zn + nz) % nz;
+        const double w = (kE19X[a] * kE19X[a] + kE19Y[a] * kE19Y[a] + kE19Z[a] * kE19Z[a]) == 1 ? 1.0 / 6.0 : 1.0 / 12.0;
+        const double v = w * psi[((size_t)zn * ny + yn) * nx + xn];
+        Sp[0] += v * kE19X[a];
+        Sp[1] += v * kE19Y[a];
+        Sp[2] += v * kE19Z[a];
+    }
+    const double rho = stage[i];
+    double fl[19], m[19];
+#pragma unroll
+    for (int a = 0; a < 19; ++a) fl[a] = (double)f[a * st + i];
+    moments19(fl, m);
+    const double drho = P.gravity ? rho - *rho_ave : 0.0;
+    const double F[3] = {P.negG * psi[i] * Sp[0] + drho * P.gx, P.negG * psi[i] * Sp[1] + drho * P.gy,
+                         P.negG * psi[i] * Sp[2] + drho * P.gz};
+    for (int c = 0; c < 3; ++c) stage[(1 + c) * nn + i] = (m[1 + c] + 0.5 * F[c]) / rho;
+}
+
+// FP64 per-workgroup sums of rho and T of the current state.
+template <typename S>
+__global__ void __launch_bounds__(256) k_sum(const S *__restrict__ f, const S *__restrict__ g, size_t st, size_t nn,
+                                             double *__restrict__ partials) {
+    __shared__ double red[2][4];
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double r = 0.0, t = 0.0;
+    if (i < nn) {
+        double fl[19], gl[7];
+#pragma unroll
+        for (int a = 0; a < 19; ++a) fl[a] = (double)f[a * st + i];
+#pragma unroll
+        for (int a = 0; a < 7; ++a) gl[a] = (double)g[a * st + i];
+        r = sum19(fl);
+        t = sum7(gl);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        r += __shfl_xor(r, o, 64);
+        t += __shfl_xor(t, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = r;
+        red[1][threadIdx.x >> 6] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+        partials[2 * blockIdx.x + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    }
+}
+
+// Sum `count` partials (with `pitch` values per entry, summing component
+// `comp`) in a fixed order and write sum * scale to *out.
+__global__ void __launch_bounds__(256) k_finish(const double *__restrict__ partials, int count, int pitch, int comp,
+                                                double scale, double *__restrict__ out) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < count; k += 256) acc += partials[(size_t)k * pitch + comp];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0] * scale;
+}
+
+}  // namespace lbm

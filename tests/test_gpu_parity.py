@@ -1,0 +1,129 @@
+"""Parity of the HIP fused step (through the C-ABI) with the FP64 oracle.
+
+FP64 storage runs the same kernels in double precision and must agree with
+the oracle to 1e-12 (rounding order only).  FP32 storage must agree to the
+stated tolerance on rho, u and T (metric in parity_util.errors)."""
+import numpy as np
+import pytest
+
+from parity_util import errors, run_gpu, run_oracle, workload
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-5
+
+
+def fp32_u_tol(steps, ref):
+    """u tolerance for FP32 population storage after `steps` steps.
+
+    Every step rounds the stored populations to FP32 (+-1/2 ulp).  The
+    momentum sum e f of a node collects ~10 of them; with f ~ w rho this is a
+    per-step error of about 5e-9 in u, which the following steps carry like a
+    random walk.  Taking the largest of ~1e6 nodes (5 sigma) and a factor 2
+    for the FP32 arithmetic of the collision gives 5e-8 sqrt(N) in |u|; the
+    relative bound is that over max|u_ref|, and never below 1e-5."""
+    umax = float(np.sqrt(ref[1] ** 2 + ref[2] ** 2 + ref[3] ** 2).max())
+    return max(FP32_TOL, 5e-8 * np.sqrt(steps) / umax)
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _check(e, tol, keys=("rho", "u", "T"), tol_u=None):
+    for k in keys:
+        t = tol_u if (k == "u" and tol_u is not None) else tol
+        assert e[k] <= t, (k, t, e)
+
+
+@pytest.mark.parametrize("steps", [1, 300])
+def test_static_droplet_fp64(steps):
+    """Static droplet, 32^3 periodic, T_sat = 0.86 Tc (FP64 kernels)."""
+    w = workload("static_droplet_32")
+    _say(f"static_droplet_32 f64 steps={steps}")
+    e = errors(run_gpu(w, steps, "f64"), run_oracle(w, steps))
+    _say(f"  errors {e}")
+    _check(e, FP64_TOL)
+
+
+@pytest.mark.parametrize("steps", [1, 300])
+def test_static_droplet_fp32(steps):
+    w = workload("static_droplet_32")
+    _say(f"static_droplet_32 f32 steps={steps}")
+    ref = run_oracle(w, steps)
+    e = errors(run_gpu(w, steps, "f32"), ref)
+    tu = fp32_u_tol(steps, ref)
+    _say(f"  errors {e} u-tolerance {tu:.3e}")
+    _check(e, FP32_TOL, tol_u=tu)
+
+
+@pytest.mark.parametrize("launch", [(64, 4, 4), (32, 8, 3), (32, 8, 16)])
+def test_non_cubic_ragged_grid_fp64(launch):
+    """24 x 20 x 17 periodic grid: ragged tiles in x, y and z chunks, and
+    distinct extents that catch axis mix-ups."""
+    w = workload("static_droplet_32", nx=24, ny=20, nz=17, radius=5.0)
+    w["init"]["center"] = [11.3, 9.6, 8.2]
+    _say(f"non-cubic f64 launch={launch}")
+    e = errors(run_gpu(w, 40, "f64", launch=launch), run_oracle(w, 40))
+    _say(f"  errors {e}")
+    _check(e, FP64_TOL)
+
+
+def test_launch_shape_does_not_change_result():
+    """Every launch shape computes each node identically (bitwise)."""
+    w = workload("static_droplet_32", nx=40, ny=36, nz=20, radius=6.0)
+    outs = []
+    for launch in [(64, 4, 4), (32, 8, 7), (64, 8, 20), (32, 16, 1), (128, 4, 5)]:
+        _say(f"launch {launch}")
+        outs.append(run_gpu(w, 25, "f32", launch=launch))
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+
+
+def test_evaporation_reduced_fp64():
+    """Droplet at T_sat in vapour 0.14 Tc hotter (constant lambda), 40^3, with
+    density noise: the full phase-change source is active."""
+    w = workload("evaporation_128", nx=40, ny=40, nz=40, radius=9.0)
+    _say("evaporation 40^3 f64")
+    e = errors(run_gpu(w, 60, "f64"), run_oracle(w, 60))
+    _say(f"  errors {e}")
+    _check(e, FP64_TOL)
+
+
+def test_pool_boiling_small_fp64():
+    """Walls: bounce-back bottom with heated patch, open top, buoyancy."""
+    w = workload("pool_boiling_32x32x48")
+    _say("pool_boiling_32x32x48 f64")
+    e = errors(run_gpu(w, 50, "f64", chunks=[1, 19, 30]), run_oracle(w, 50))
+    _say(f"  errors {e}")
+    _check(e, FP64_TOL)
+
+
+def test_pool_boiling_small_fp32():
+    w = workload("pool_boiling_32x32x48")
+    _say("pool_boiling_32x32x48 f32")
+    ref = run_oracle(w, 50)
+    e = errors(run_gpu(w, 50, "f32"), ref)
+    tu = fp32_u_tol(50, ref)
+    _say(f"  errors {e} u-tolerance {tu:.3e}")
+    _check(e, FP32_TOL, tol_u=tu)
+
+
+def test_thermal_frozen_flat_interface_fp64():
+    """thermal = 0 holds the temperature lattice fixed (isothermal runs)."""
+    w = workload("flat_interface_128", nx=3, ny=2, nz=64)
+    _say("flat interface thermal=0 f64")
+    e = errors(run_gpu(w, 200, "f64"), run_oracle(w, 200))
+    _say(f"  errors {e}")
+    _check(e, FP64_TOL)
+
+
+def test_constant_chi_and_minimal_grid_fp64():
+    """Constant chi, a 1 x 1 x 5 grid (every neighbour wraps onto the column)."""
+    w = workload("flat_interface_128", nx=1, ny=1, nz=5, kappa_mode=1, kappa=0.05, thermal=1)
+    _say("1x1x5 f64")
+    e = errors(run_gpu(w, 30, "f64"), run_oracle(w, 30))
+    _say(f"  errors {e}")
+    _check(e, FP64_TOL, keys=("rho", "T"))

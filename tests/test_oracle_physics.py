@@ -24,9 +24,10 @@ def coexistence(frac=0.86):
     return Tc, frac * Tc, rl, rg
 
 
-def sigma_default():
+def sigma_default(a="a=2/49"):
+    """Calibrated sigma for the EOS constant a (the oracle's default a = 2/49)."""
     with open(workloads().WORKLOADS_JSON) as fh:
-        return json.load(fh)["sigma_default"]
+        return json.load(fh)["sigma_default"][a]
 
 
 def droplet_sim(oracle_lib, n=16, radius=4.0, center=None, thermal=1, noise=0.0, **kw):
