@@ -98,10 +98,17 @@ def main():
         n = args.copy_probe * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda:0")
         b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
         for _ in range(20):
             b.copy_(a)
+        end.record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "calls": 20}))
+        sec = start.elapsed_time(end) / 1e3 / 20
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "calls": 21,
+                          "copy_probe_GBps": round(8 * n / sec / 1e9, 1)}))
         return
 
     from paper_2201_06039_amd import lbm, workloads as W

@@ -24,14 +24,15 @@ constexpr TileShape kTiles[] = {{64, 4}, {32, 8}, {64, 8}, {32, 16}, {128, 4}};
 
 struct Layout {
     size_t nn, stride, es, cs;
-    size_t off_f[2], off_g[2], off_phi, off_stage, off_part, off_scal, total;
+    size_t off_pop[2], off_phi, off_stage, off_part, off_scal, total;
     size_t max_partials;
 };
 
 bool valid_params(const lbm_params *p) {
     if (!p) return false;
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return false;
-    if ((size_t)p->nx * p->ny * p->nz >= (size_t)1 << 31) return false;
+    // node byte offsets inside a plane set must fit in 32 bits
+    if ((size_t)p->nx * p->ny * p->nz * (p->storage == LBM_STORE_F64 ? 8 : 4) >= (size_t)1 << 32) return false;
     if (p->bc_z != LBM_BC_PERIODIC && p->bc_z != LBM_BC_WALL_BOTTOM_OPEN_TOP) return false;
     if (p->bc_z == LBM_BC_WALL_BOTTOM_OPEN_TOP && p->nz < 3) return false;
     if (!(p->tau_e > 0.5) || !(p->tau_v > 0.5) || !(p->tau_q > 0.5) || !(p->tau_pi > 0.5)) return false;
@@ -63,14 +64,12 @@ Layout make_layout(const lbm_params *p) {
     L.es = p->storage == LBM_STORE_F64 ? 8 : 4;
     L.cs = L.es;
     L.stride = align_up(L.nn, 64);
+    // Each ping-pong copy holds its 26 population planes contiguously:
+    // f_0..f_18 then g_0..g_6, `stride` elements apart.
     size_t off = 0;
     for (int k = 0; k < 2; ++k) {
-        L.off_f[k] = off;
-        off = align_up(off + 19 * L.stride * L.es, kAlign);
-    }
-    for (int k = 0; k < 2; ++k) {
-        L.off_g[k] = off;
-        off = align_up(off + 7 * L.stride * L.es, kAlign);
+        L.off_pop[k] = off;
+        off = align_up(off + 26 * L.stride * L.es, kAlign);
     }
     L.off_phi = off;
     off = align_up(off + L.stride * L.cs, kAlign);
@@ -153,8 +152,8 @@ struct lbm_handle {
     double *energy() { return (double *)(arena + L.off_scal + 2 * sizeof(double)); }
     double *stage() { return (double *)(arena + L.off_stage); }
     double *partials() { return (double *)(arena + L.off_part); }
-    void *f(int k) { return arena + L.off_f[k]; }
-    void *g(int k) { return arena + L.off_g[k]; }
+    void *f(int k) { return arena + L.off_pop[k]; }
+    void *g(int k) { return arena + L.off_pop[k] + 19 * L.stride * L.es; }
     void *phi() { return arena + L.off_phi; }
 };
 
@@ -162,18 +161,32 @@ namespace {
 
 int hip_status(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EHIP; }
 
+// Default launch shape (measured on MI355X): tiles as wide as the rows allow
+// (128 nodes: whole 512-byte rows, and the x halo wraps inside the tile when
+// nx = 128), 4 rows, and chunks of 16-32 planes; the z halo of a chunk is read
+// twice, so chunks are kept long unless the grid would then give fewer
+// workgroups than the 256 compute units.
 void set_default_launch(lbm_handle *h) {
-    h->tile_x = 64;
-    h->tile_y = 4;
-    if (h->p.nx <= 32) {
+    const int nx = h->p.nx, ny = h->p.ny, nz = h->p.nz;
+    if (nx >= 96) {
+        h->tile_x = 128;
+        h->tile_y = 4;
+    } else if (nx > 32) {
+        h->tile_x = 64;
+        h->tile_y = 4;
+    } else {
         h->tile_x = 32;
         h->tile_y = 8;
     }
-    // Aim at about 2048 workgroups, at least 4 planes per chunk.
-    const long tiles = (long)((h->p.nx + h->tile_x - 1) / h->tile_x) * ((h->p.ny + h->tile_y - 1) / h->tile_y);
-    long cz = (long)h->p.nz * tiles / 2048;
+    if (h->p.storage == LBM_STORE_F64 && h->tile_x * h->tile_y != 256) {
+        h->tile_x = nx > 32 ? 64 : 32;
+        h->tile_y = nx > 32 ? 4 : 8;
+    }
+    const long tiles = (long)((nx + h->tile_x - 1) / h->tile_x) * ((ny + h->tile_y - 1) / h->tile_y);
+    long cz = (long)nz * tiles / 256;
+    if (cz > 32) cz = 32;
     if (cz < 4) cz = 4;
-    if (cz > h->p.nz) cz = h->p.nz;
+    if (cz > nz) cz = nz;
     h->chunk_z = (int)cz;
 }
 
@@ -182,9 +195,15 @@ int workgroups_for(const lbm_handle *h, int tx, int ty, int cz) {
     return (int)n;
 }
 
+// The buffer-resource path needs the 26 planes of a copy within 32-bit offsets.
+bool buffer_path(const Layout &L) { return 26 * L.stride * L.es <= 0xFFFFFFFFull; }
+
 template <typename S, typename C, int TX, int TY, bool WALLS>
 int launch_step_t(lbm_handle *h, const lbm::StepArgs<S, C> &A, int nb) {
-    hipLaunchKernelGGL((lbm::k_step<S, C, TX, TY, WALLS>), dim3(nb), dim3(TX * TY), 0, h->stream, A);
+    if (buffer_path(h->L))
+        hipLaunchKernelGGL((lbm::k_step<S, C, TX, TY, WALLS, true>), dim3(nb), dim3(TX * TY), 0, h->stream, A);
+    else
+        hipLaunchKernelGGL((lbm::k_step<S, C, TX, TY, WALLS, false>), dim3(nb), dim3(TX * TY), 0, h->stream, A);
     return hip_status(hipGetLastError());
 }
 
@@ -208,10 +227,8 @@ template <typename S, typename C>
 int step_once(lbm_handle *h) {
     lbm::StepArgs<S, C> A;
     const int c = h->cur, n = 1 - c;
-    A.f_in = (const S *)h->f(c);
-    A.f_out = (S *)h->f(n);
-    A.g_in = (const S *)h->g(c);
-    A.g_out = (S *)h->g(n);
+    A.pop_in = (const S *)h->f(c);
+    A.pop_out = (S *)h->f(n);
     A.phi = (C *)h->phi();
     A.rho_ave = h->rho_ave();
     A.partials = h->partials();

@@ -212,10 +212,8 @@ __device__ __forceinline__ void equilibrium19(C rho, C ux, C uy, C uz, C *meq) {
 
 template <typename S, typename C>
 struct StepArgs {
-    const S *__restrict__ f_in;
-    S *__restrict__ f_out;
-    const S *__restrict__ g_in;
-    S *__restrict__ g_out;
+    const S *__restrict__ pop_in;   // 26 planes: f_0..f_18, g_0..g_6, `stride` elements apart
+    S *__restrict__ pop_out;
     C *__restrict__ phi;
     const double *__restrict__ rho_ave;
     double *__restrict__ partials;  // per-workgroup sum of rho (when gravity is on)
@@ -234,28 +232,78 @@ __device__ __forceinline__ int xcd_logical_block(int b, int nb) {
     return xcd * q + (xcd < r ? xcd : r) + (b >> 3);
 }
 
-// Loads and stores at a 32-bit byte offset from a uniform base: the base stays
-// in SGPRs and the access uses the scalar-base + 32-bit vector-offset form, so
-// no 64-bit address arithmetic is spent per access.
-template <typename T>
-__device__ __forceinline__ T ldg(const T *base, unsigned boff) {
-    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + boff);
-}
-template <typename T>
-__device__ __forceinline__ void stg(T *base, unsigned boff, T v) {
-    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + boff) = v;
-}
-
 // a * b + c rounded once (the library is built without automatic contraction,
 // so every fused operation is one of these and the rounding is fixed).
 __device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-template <typename S, typename C, int TX, int TY, bool WALLS>
+// Access to the 26 population planes of the two ping-pong copies.
+//  BUF = true: one buffer resource per copy; a population access is
+//  `plane * stride_bytes` (a scalar offset) + the node's byte offset (a 32-bit
+//  vector offset shared by all 26 planes), so no vector address arithmetic is
+//  spent on loads.  Needs the 26 planes of a copy to span less than 4 GiB.
+//  BUF = false: plain global pointers (any size).
+template <typename S, bool BUF>
+struct PopIO;
+
+template <typename S>
+struct BufBits;
+template <>
+struct BufBits<float> {
+    __device__ static float ld(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
+    }
+    __device__ static void st(float x, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v, s, 0);
+    }
+};
+template <>
+struct BufBits<double> {
+    __device__ static double ld(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
+    }
+    __device__ static void st(double x, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+        typedef unsigned v2u __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, x), r, v, s, 0);
+    }
+};
+
+constexpr int kBufferFlags = 0x00020000;  // raw dword buffer; the record count is left at its maximum and
+                                          // every offset is kept inside the 26 planes by construction
+
+template <typename S>
+struct PopIO<S, true> {
+    __amdgpu_buffer_rsrc_t in, out;
+    unsigned sb;  // plane stride in bytes
+    __device__ PopIO(const S *pin, S *pout, size_t stride) {
+        sb = (unsigned)(stride * sizeof(S));
+        in = __builtin_amdgcn_make_buffer_rsrc(const_cast<S *>(pin), 0, -1, kBufferFlags);
+        out = __builtin_amdgcn_make_buffer_rsrc(pout, 0, -1, kBufferFlags);
+    }
+    __device__ S load(int a, unsigned boff) const { return BufBits<S>::ld(in, boff, (unsigned)a * sb); }
+    __device__ void store(int a, unsigned boff, S v) const { BufBits<S>::st(v, out, boff, (unsigned)a * sb); }
+};
+
+template <typename S>
+struct PopIO<S, false> {
+    const S *in;
+    S *out;
+    size_t st;
+    __device__ PopIO(const S *pin, S *pout, size_t stride) : in(pin), out(pout), st(stride) {}
+    __device__ S load(int a, unsigned boff) const {
+        return *reinterpret_cast<const S *>(reinterpret_cast<const char *>(in + a * st) + boff);
+    }
+    __device__ void store(int a, unsigned boff, S v) const {
+        *reinterpret_cast<S *>(reinterpret_cast<char *>(out + a * st) + boff) = v;
+    }
+};
+
+template <typename S, typename C, int TX, int TY, bool WALLS, bool BUF>
 __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<S, C> A) {
     constexpr int NT = TX * TY, EX = TX + 2, EY = TY + 2, NE = EX * EY, NH = NE - NT;
     static_assert(NH <= NT, "halo must not exceed the tile");
     constexpr unsigned ES = sizeof(S);
+    constexpr int G0 = 19;  // first D3Q7 plane
     __shared__ C s_psi[4][NE];
     __shared__ C s_rho[4][NE];
     __shared__ double s_red[NT / 64];
@@ -263,7 +311,7 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<S, C> A) {
     const Phys<C> &P = A.P;
     const int nx = A.nx, ny = A.ny, nz = A.nz;
     const unsigned plane = (unsigned)nx * (unsigned)ny;
-    const size_t st = A.stride;
+    const PopIO<S, BUF> io(A.pop_in, A.pop_out, A.stride);
 
     const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
     const int itx = logical % A.ntx;
@@ -304,25 +352,33 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<S, C> A) {
         return zz < 0 ? zz + nz : zz;
     };
 
-    // rho, T, psi of plane zp for the tile and its halo -> LDS slot.
-    auto moments_plane = [&](int zp, int slot, C *kf, C *kg, C &krho, C &kT, C &kpsi) {
+    // Populations of plane zp for this thread's tile node (kf, kg) and its
+    // halo node (hf, hg).
+    auto load_plane = [&](int zp, C *kf, C *kg, C *hf, C *hg) {
         const unsigned zoff = (unsigned)zmap(zp) * plane;
         const unsigned ib = (zoff + irow) * ES;
 #pragma unroll
-        for (int a = 0; a < 19; ++a) kf[a] = (C)ldg(A.f_in + a * st, ib);
+        for (int a = 0; a < 19; ++a) kf[a] = (C)io.load(a, ib);
 #pragma unroll
-        for (int a = 0; a < 7; ++a) kg[a] = (C)ldg(A.g_in + a * st, ib);
-        C hf[19], hg[7];
+        for (int a = 0; a < 7; ++a) kg[a] = (C)io.load(G0 + a, ib);
         if (has_halo) {
             const unsigned hb = (zoff + hrow) * ES;
 #pragma unroll
-            for (int a = 0; a < 19; ++a) hf[a] = (C)ldg(A.f_in + a * st, hb);
+            for (int a = 0; a < 19; ++a) hf[a] = (C)io.load(a, hb);
 #pragma unroll
-            for (int a = 0; a < 7; ++a) hg[a] = (C)ldg(A.g_in + a * st, hb);
+            for (int a = 0; a < 7; ++a) hg[a] = (C)io.load(G0 + a, hb);
         }
+    };
+
+    // rho, T, psi of a loaded plane (tile node and halo node) -> LDS slot.
+    auto plane_moments = [&](int slot, const C *kf, const C *kg, const C *hf, const C *hg, C &krho, C &kT,
+                             C &kpsi) {
         const C rho = sum19(kf), T = sum7(kg);
         const C p2 = psi_squared(P, rho, T);
-        if (active && (!(rho > C(0)) || !(p2 >= C(0)))) atomicOr(A.status, 1u);
+        // Unstable node (rho <= 0, psi^2 < 0 or NaN): one flag update per wave.
+        const bool bad = active && (!(rho > C(0)) || !(p2 >= C(0)));
+        const unsigned long long badmask = __ballot(bad);
+        if (badmask && __lane_id() == (unsigned)(__ffsll(badmask) - 1)) atomicOr(A.status, 1u);
         const C psi = Num<C>::sqrt(p2 > C(0) ? p2 : C(0));
         s_psi[slot][li] = psi;
         s_rho[slot][li] = rho;
@@ -348,23 +404,13 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<S, C> A) {
         T_bottom = (C)(dx * dx + dy * dy <= P.patch_r2 ? P.T_patch : P.T_wall);
     }
     const C rho_ave = (C)(*A.rho_ave);
-
-    C cf[19], cg[7], c_rho, c_T, c_psi;
-    C nf[19], ng[7], n_rho, n_T, n_psi;
-    {
-        C tf[19], tg[7], t0, t1, t2;
-        moments_plane(z0 - 1, 0, tf, tg, t0, t1, t2);
-    }
-    moments_plane(z0, 1, cf, cg, c_rho, c_T, c_psi);
     double rho_sum = 0.0;
 
-    for (int z = z0; z < zend; ++z) {
-        const int s = z - z0 + 1;
-        moments_plane(z + 1, (s + 1) & 3, nf, ng, n_rho, n_T, n_psi);
-        __syncthreads();
-        if (active) {
-            const int sm = (s + 3) & 3, s0 = s & 3, sp = (s + 1) & 3;
-            // Eq. (7) and the isotropic gradient: omega(1) = 1/6, omega(2) = 1/12.
+    // Collision and streaming of the tile node at plane z (slot s of the ring
+    // holds plane z; s-1 and s+1 its neighbours).
+    auto collide_stream = [&](int z, int s, const C *cf, const C *cg, C rho, C T, C psi) {
+        const int sm = (s + 3) & 3, s0 = s & 3, sp = (s + 1) & 3;
+        // Eq. (7) and the isotropic gradient: omega(1) = 1/6, omega(2) = 1/12.
 #define NB(arr, sl, dx, dy) arr[sl][li + (dy) * EX + (dx)]
 #define STENCIL(arr, OX, OY, OZ)                                                                                    \
     {                                                                                                               \
@@ -375,198 +421,230 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<S, C> A) {
         OY = fmad(C(1.0 / 6.0), NB(arr, s0, 0, 1) - NB(arr, s0, 0, -1), C(1.0 / 12.0) * ((xy - xmy) + (yz + ymz))); \
         OZ = fmad(C(1.0 / 6.0), NB(arr, sp, 0, 0) - NB(arr, sm, 0, 0), C(1.0 / 12.0) * ((xz - xmz) + (yz - ymz))); \
     }
-            C Spx, Spy, Spz, grx, gry, grz;
-            STENCIL(s_psi, Spx, Spy, Spz)
-            STENCIL(s_rho, grx, gry, grz)
+        C Spx, Spy, Spz, grx, gry, grz;
+        STENCIL(s_psi, Spx, Spy, Spz)
+        STENCIL(s_rho, grx, gry, grz)
 #undef STENCIL
 #undef NB
-            const C rho = c_rho, T = c_T, psi = c_psi;
-            const C inv_rho = Num<C>::rcp(rho);
-            const C gpsi = P.negG * psi;
-            const C fmx = gpsi * Spx, fmy = gpsi * Spy, fmz = gpsi * Spz;
-            C Fx = fmx, Fy = fmy, Fz = fmz;
-            if (P.gravity) {
-                const C drho = rho - rho_ave;
-                Fx = fmad(drho, P.gx, Fx);
-                Fy = fmad(drho, P.gy, Fy);
-                Fz = fmad(drho, P.gz, Fz);
-            }
-            // Moments as deviations from the rest equilibrium w rho: the rest
-            // part is conserved by the collision (Lambda_0 = 1, S_0 = 0, and
-            // m_eq(rho, 0) relaxes onto itself), so it is added back to f*
-            // at the end instead of being carried through O(rho) sums.
-            C m[19];
-            moments19<C, true>(cf, m, rho);
-            // Eq. (10)
-            const C ux = fmad(C(0.5), Fx, m[1]) * inv_rho;
-            const C uy = fmad(C(0.5), Fy, m[2]) * inv_rho;
-            const C uz = fmad(C(0.5), Fz, m[3]) * inv_rho;
-            // Eq. (5) for m5..m15, and the deviations from m_eq(rho, 0) of m4
-            // and m16..m18 (m4 - rho, m16..18 - rho/9).
-            constexpr C cs2 = C(1.0 / 3.0);
-            const C ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
-            const C rux = rho * ux, ruy = rho * uy, ruz = rho * uz;
-            const C r3 = rho * cs2;
-            const C rxx = rux * ux, ryy = ruy * uy, rzz = ruz * uz;  // rho u_i^2
-            const C r6 = C(0.5) * cs2 * (rxx + ryy + rzz);           // rho |u|^2 / 6
-            C meq[19];
-            meq[4] = rxx + ryy + rzz;
-            meq[5] = C(2) * rxx - ryy - rzz;
-            meq[6] = ryy - rzz;
-            meq[7] = rux * uy;
-            meq[8] = rux * uz;
-            meq[9] = ruy * uz;
-            meq[10] = fmad(rxx, uy, r3 * uy);
-            meq[11] = fmad(ryy, ux, r3 * ux);
-            meq[12] = fmad(rxx, uz, r3 * uz);
-            meq[13] = fmad(rzz, ux, r3 * ux);
-            meq[14] = fmad(ryy, uz, r3 * uz);
-            meq[15] = fmad(rzz, uy, r3 * uy);
-            meq[16] = fmad(cs2, rxx + ryy, -r6);
-            meq[17] = fmad(cs2, rxx + rzz, -r6);
-            meq[18] = fmad(cs2, ryy + rzz, -r6);
-            (void)ux2; (void)uy2; (void)uz2;
-            // Eq. (9)
-            const C xFx = ux * Fx, yFy = uy * Fy, zFz = uz * Fz;
-            const C Fu = xFx + yFy + zFz;
-            const C fm2 = fmad(fmx, fmx, fmad(fmy, fmy, fmz * fmz));
-            const C S4 = fmad(P.sig6 * fm2, Num<C>::rcp(psi * psi), C(2) * Fu);
-            // Eq. (3): m* = m + Lambda (m_eq - m) + (I - Lambda/2) S
-            C ms[19];
-            ms[0] = C(0);
-            ms[1] = m[1] + Fx;
-            ms[2] = m[2] + Fy;
-            ms[3] = m[3] + Fz;
-            ms[4] = fmad(P.lam_e, meq[4] - m[4], fmad(C(1) - C(0.5) * P.lam_e, S4, m[4]));
-            const C hv = C(1) - C(0.5) * P.lam_v;
-            ms[5] = fmad(P.lam_v, meq[5] - m[5], fmad(hv * C(2), C(2) * xFx - yFy - zFz, m[5]));
-            ms[6] = fmad(P.lam_v, meq[6] - m[6], fmad(hv * C(2), yFy - zFz, m[6]));
-            ms[7] = fmad(P.lam_v, meq[7] - m[7], fmad(hv, fmad(Fx, uy, Fy * ux), m[7]));
-            ms[8] = fmad(P.lam_v, meq[8] - m[8], fmad(hv, fmad(Fx, uz, Fz * ux), m[8]));
-            ms[9] = fmad(P.lam_v, meq[9] - m[9], fmad(hv, fmad(Fy, uz, Fz * uy), m[9]));
-            const C hq = (C(1) - C(0.5) * P.lam_q) * cs2;
-            ms[10] = fmad(P.lam_q, meq[10] - m[10], fmad(hq, Fy, m[10]));
-            ms[11] = fmad(P.lam_q, meq[11] - m[11], fmad(hq, Fx, m[11]));
-            ms[12] = fmad(P.lam_q, meq[12] - m[12], fmad(hq, Fz, m[12]));
-            ms[13] = fmad(P.lam_q, meq[13] - m[13], fmad(hq, Fx, m[13]));
-            ms[14] = fmad(P.lam_q, meq[14] - m[14], fmad(hq, Fz, m[14]));
-            ms[15] = fmad(P.lam_q, meq[15] - m[15], fmad(hq, Fy, m[15]));
-            const C hp = (C(1) - C(0.5) * P.lam_pi) * C(2) * cs2;
-            ms[16] = fmad(P.lam_pi, meq[16] - m[16], fmad(hp, xFx + yFy, m[16]));
-            ms[17] = fmad(P.lam_pi, meq[17] - m[17], fmad(hp, xFx + zFz, m[17]));
-            ms[18] = fmad(P.lam_pi, meq[18] - m[18], fmad(hp, yFy + zFz, m[18]));
-            C fs[19];
-            populations19(ms, fs);
-            {
-                // rest part w rho; r0 closes the sum exactly, since the
-                // rounded weights 1/3 + 6/18 + 12/36 do not add up to 1.
-                const C r1 = rho * C(1.0 / 18.0), r2 = rho * C(1.0 / 36.0);
-                const C r0 = rho - fmad(C(6), r1, C(12) * r2);
-                fs[0] += r0;
+        const C inv_rho = Num<C>::rcp(rho);
+        const C gpsi = P.negG * psi;
+        const C fmx = gpsi * Spx, fmy = gpsi * Spy, fmz = gpsi * Spz;
+        C Fx = fmx, Fy = fmy, Fz = fmz;
+        if (P.gravity) {
+            const C drho = rho - rho_ave;
+            Fx = fmad(drho, P.gx, Fx);
+            Fy = fmad(drho, P.gy, Fy);
+            Fz = fmad(drho, P.gz, Fz);
+        }
+        // Moments as deviations from the rest equilibrium w rho: the rest
+        // part is conserved by the collision (Lambda_0 = 1, S_0 = 0, and
+        // m_eq(rho, 0) relaxes onto itself), so it is added back to f* at the
+        // end instead of being carried through O(rho) sums.
+        C m[19];
+        moments19<C, true>(cf, m, rho);
+        // Eq. (10)
+        const C ux = fmad(C(0.5), Fx, m[1]) * inv_rho;
+        const C uy = fmad(C(0.5), Fy, m[2]) * inv_rho;
+        const C uz = fmad(C(0.5), Fz, m[3]) * inv_rho;
+        // Eq. (5) for m5..m15, and the deviations from m_eq(rho, 0) of m4
+        // and m16..m18 (m4 - rho, m16..18 - rho/9).
+        constexpr C cs2 = C(1.0 / 3.0);
+        const C rux = rho * ux, ruy = rho * uy, ruz = rho * uz;
+        const C r3 = rho * cs2;
+        const C rxx = rux * ux, ryy = ruy * uy, rzz = ruz * uz;  // rho u_i^2
+        const C r6 = C(0.5) * cs2 * (rxx + ryy + rzz);           // rho |u|^2 / 6
+        C meq[19];
+        meq[4] = rxx + ryy + rzz;
+        meq[5] = C(2) * rxx - ryy - rzz;
+        meq[6] = ryy - rzz;
+        meq[7] = rux * uy;
+        meq[8] = rux * uz;
+        meq[9] = ruy * uz;
+        meq[10] = fmad(rxx, uy, r3 * uy);
+        meq[11] = fmad(ryy, ux, r3 * ux);
+        meq[12] = fmad(rxx, uz, r3 * uz);
+        meq[13] = fmad(rzz, ux, r3 * ux);
+        meq[14] = fmad(ryy, uz, r3 * uz);
+        meq[15] = fmad(rzz, uy, r3 * uy);
+        meq[16] = fmad(cs2, rxx + ryy, -r6);
+        meq[17] = fmad(cs2, rxx + rzz, -r6);
+        meq[18] = fmad(cs2, ryy + rzz, -r6);
+        // Eq. (9)
+        const C xFx = ux * Fx, yFy = uy * Fy, zFz = uz * Fz;
+        const C Fu = xFx + yFy + zFz;
+        const C fm2 = fmad(fmx, fmx, fmad(fmy, fmy, fmz * fmz));
+        const C S4 = fmad(P.sig6 * fm2, Num<C>::rcp(psi * psi), C(2) * Fu);
+        // Eq. (3): m* = m + Lambda (m_eq - m) + (I - Lambda/2) S
+        C ms[19];
+        ms[0] = C(0);
+        ms[1] = m[1] + Fx;
+        ms[2] = m[2] + Fy;
+        ms[3] = m[3] + Fz;
+        ms[4] = fmad(P.lam_e, meq[4] - m[4], fmad(C(1) - C(0.5) * P.lam_e, S4, m[4]));
+        const C hv = C(1) - C(0.5) * P.lam_v;
+        ms[5] = fmad(P.lam_v, meq[5] - m[5], fmad(hv * C(2), C(2) * xFx - yFy - zFz, m[5]));
+        ms[6] = fmad(P.lam_v, meq[6] - m[6], fmad(hv * C(2), yFy - zFz, m[6]));
+        ms[7] = fmad(P.lam_v, meq[7] - m[7], fmad(hv, fmad(Fx, uy, Fy * ux), m[7]));
+        ms[8] = fmad(P.lam_v, meq[8] - m[8], fmad(hv, fmad(Fx, uz, Fz * ux), m[8]));
+        ms[9] = fmad(P.lam_v, meq[9] - m[9], fmad(hv, fmad(Fy, uz, Fz * uy), m[9]));
+        const C hq = (C(1) - C(0.5) * P.lam_q) * cs2;
+        ms[10] = fmad(P.lam_q, meq[10] - m[10], fmad(hq, Fy, m[10]));
+        ms[11] = fmad(P.lam_q, meq[11] - m[11], fmad(hq, Fx, m[11]));
+        ms[12] = fmad(P.lam_q, meq[12] - m[12], fmad(hq, Fz, m[12]));
+        ms[13] = fmad(P.lam_q, meq[13] - m[13], fmad(hq, Fx, m[13]));
+        ms[14] = fmad(P.lam_q, meq[14] - m[14], fmad(hq, Fz, m[14]));
+        ms[15] = fmad(P.lam_q, meq[15] - m[15], fmad(hq, Fy, m[15]));
+        const C hp = (C(1) - C(0.5) * P.lam_pi) * C(2) * cs2;
+        ms[16] = fmad(P.lam_pi, meq[16] - m[16], fmad(hp, xFx + yFy, m[16]));
+        ms[17] = fmad(P.lam_pi, meq[17] - m[17], fmad(hp, xFx + zFz, m[17]));
+        ms[18] = fmad(P.lam_pi, meq[18] - m[18], fmad(hp, yFy + zFz, m[18]));
+        C fs[19];
+        populations19(ms, fs);
+        {
+            // rest part w rho; r0 closes the sum exactly, since the rounded
+            // weights 1/3 + 6/18 + 12/36 do not add up to 1.
+            const C r1 = rho * C(1.0 / 18.0), r2 = rho * C(1.0 / 36.0);
+            const C r0 = rho - fmad(C(6), r1, C(12) * r2);
+            fs[0] += r0;
 #pragma unroll
-                for (int a = 1; a < 7; ++a) fs[a] += r1;
+            for (int a = 1; a < 7; ++a) fs[a] += r1;
 #pragma unroll
-                for (int a = 7; a < 19; ++a) fs[a] += r2;
-            }
+            for (int a = 7; a < 19; ++a) fs[a] += r2;
+        }
 
-            // ---- D3Q7 thermal lattice ----
-            C gp[7];
-            const unsigned own = (unsigned)z * plane + irow;
-            if (P.thermal) {
-                // Eq. (48): local velocity divergence (pre-collision m_4).
-                const C divu = fmad(P.divu_b, S4, -fmad(P.divu_a, m[4] - meq[4], C(2) * Fu)) * (C(1.5) * inv_rho);
-                // Eq. (38): n = N g
-                const C n1 = cg[1] - cg[2], n2 = cg[3] - cg[4], n3 = cg[5] - cg[6];
-                const C a12 = cg[1] + cg[2], a34 = cg[3] + cg[4], a56 = cg[5] + cg[6];
-                const C n5 = a12 - a34, n6 = a12 - a56;
-                const C chi = P.kappa_mode ? P.kappa : P.kappa * inv_rho * P.inv_cV;
-                const C inv_vsT = Num<C>::rcp(fmad(chi, P.inv_csT2, C(0.5)));
-                // Eq. (45): local temperature gradient.
-                const C kgr = -inv_vsT * P.inv_csT2;
-                const C dTx = kgr * n1, dTy = kgr * n2, dTz = kgr * n3;
-                // Eq. (18) with (dp/dT)_rho = rho R/(1 - b rho), constant c_V.
-                const C cr = chi * inv_rho;
-                const C adv = fmad(fmad(cr, grx, -ux), dTx, fmad(fmad(cr, gry, -uy), dTy, fmad(cr, grz, -uz) * dTz));
-                const C phis = fmad(-T * P.R * P.inv_cV, Num<C>::rcp(fmad(-P.b, rho, C(1))) * divu, adv);
-                // Eq. (39) with Eq. (42)-(43); n4 is carried as its deviation
-                // n4 - d T = (1 - d) T - g0 from the equilibrium.
-                const C keep = C(1) - inv_vsT;
-                const C s1 = n1 * keep, s2 = n2 * keep, s3 = n3 * keep;
-                const C s4 = fmad(P.wT0, T, -cg[0]) * (C(1) - P.gam_q);
-                const C s5 = n5 * (C(1) - P.gam_pi), s6 = n6 * (C(1) - P.gam_pi);
-                // Eqs. (23)-(24): Q = w (1.5 phi_s - 0.5 phi_s(t-1))
-                const unsigned ob = own * (unsigned)sizeof(C);
-                const C qs = fmad(C(1.5), phis, C(-0.5) * ldg(A.phi, ob));
-                const C Q0 = P.wT0 * qs, Q1 = P.wT1 * qs;
-                // Eq. (40)-(41): g+ = N^-1 n* + Q = w T + N^-1 (n* - n_eq) + Q
-                const C wT = P.wT1 * T;
-                const C c456 = (s4 + s5 + s6) * C(1.0 / 6.0);
-                const C c3 = (s4 - C(2) * s5 + s6) * C(1.0 / 6.0), c5 = (s4 + s5 - C(2) * s6) * C(1.0 / 6.0);
-                gp[0] = (T - C(6) * wT) - s4 + Q0;
-                gp[1] = wT + (fmad(C(0.5), s1, c456) + Q1);
-                gp[2] = wT + (fmad(C(-0.5), s1, c456) + Q1);
-                gp[3] = wT + (fmad(C(0.5), s2, c3) + Q1);
-                gp[4] = wT + (fmad(C(-0.5), s2, c3) + Q1);
-                gp[5] = wT + (fmad(C(0.5), s3, c5) + Q1);
-                gp[6] = wT + (fmad(C(-0.5), s3, c5) + Q1);
-                stg(A.phi, ob, phis);
-            }
+        // ---- D3Q7 thermal lattice ----
+        C gp[7];
+        const unsigned own = (unsigned)z * plane + irow;
+        if (P.thermal) {
+            // Eq. (48): local velocity divergence (pre-collision m_4).
+            const C divu = fmad(P.divu_b, S4, -fmad(P.divu_a, m[4] - meq[4], C(2) * Fu)) * (C(1.5) * inv_rho);
+            // Eq. (38): n = N g
+            const C n1 = cg[1] - cg[2], n2 = cg[3] - cg[4], n3 = cg[5] - cg[6];
+            const C a12 = cg[1] + cg[2], a34 = cg[3] + cg[4], a56 = cg[5] + cg[6];
+            const C n5 = a12 - a34, n6 = a12 - a56;
+            const C chi = P.kappa_mode ? P.kappa : P.kappa * inv_rho * P.inv_cV;
+            const C inv_vsT = Num<C>::rcp(fmad(chi, P.inv_csT2, C(0.5)));
+            // Eq. (45): local temperature gradient.
+            const C kgr = -inv_vsT * P.inv_csT2;
+            const C dTx = kgr * n1, dTy = kgr * n2, dTz = kgr * n3;
+            // Eq. (18) with (dp/dT)_rho = rho R/(1 - b rho), constant c_V.
+            const C cr = chi * inv_rho;
+            const C adv = fmad(fmad(cr, grx, -ux), dTx, fmad(fmad(cr, gry, -uy), dTy, fmad(cr, grz, -uz) * dTz));
+            const C phis = fmad(-T * P.R * P.inv_cV, Num<C>::rcp(fmad(-P.b, rho, C(1))) * divu, adv);
+            // Eq. (39) with Eq. (42)-(43); n4 is carried as its deviation
+            // n4 - d T = (1 - d) T - g0 from the equilibrium.
+            const C keep = C(1) - inv_vsT;
+            const C s1 = n1 * keep, s2 = n2 * keep, s3 = n3 * keep;
+            const C s4 = fmad(P.wT0, T, -cg[0]) * (C(1) - P.gam_q);
+            const C s5 = n5 * (C(1) - P.gam_pi), s6 = n6 * (C(1) - P.gam_pi);
+            // Eqs. (23)-(24): Q = w (1.5 phi_s - 0.5 phi_s(t-1))
+            C *phi_own = A.phi + own;
+            const C qs = fmad(C(1.5), phis, C(-0.5) * *phi_own);
+            const C Q0 = P.wT0 * qs, Q1 = P.wT1 * qs;
+            // Eq. (40)-(41): g+ = N^-1 n* + Q = w T + N^-1 (n* - n_eq) + Q
+            const C wT = P.wT1 * T;
+            const C c456 = (s4 + s5 + s6) * C(1.0 / 6.0);
+            const C c3 = (s4 - C(2) * s5 + s6) * C(1.0 / 6.0), c5 = (s4 + s5 - C(2) * s6) * C(1.0 / 6.0);
+            gp[0] = (T - C(6) * wT) - s4 + Q0;
+            gp[1] = wT + (fmad(C(0.5), s1, c456) + Q1);
+            gp[2] = wT + (fmad(C(-0.5), s1, c456) + Q1);
+            gp[3] = wT + (fmad(C(0.5), s2, c3) + Q1);
+            gp[4] = wT + (fmad(C(-0.5), s2, c3) + Q1);
+            gp[5] = wT + (fmad(C(0.5), s3, c5) + Q1);
+            gp[6] = wT + (fmad(C(-0.5), s3, c5) + Q1);
+            *phi_own = phis;
+        }
 
-            // ---- streaming (push), Eq. (4) and Eq. (40) ----
-            const unsigned PB = plane * ES;
-            const unsigned Zc = (unsigned)z * PB;
-            unsigned Zo[3];
+        // ---- streaming (push), Eq. (4) and Eq. (40) ----
+        const unsigned PB = plane * ES;
+        const unsigned Zc = (unsigned)z * PB;
+        unsigned Zo[3];
+        if (WALLS) {
+            Zo[0] = z > 0 ? Zc - PB : 0u;
+            Zo[1] = Zc;
+            Zo[2] = z < nz - 1 ? Zc + PB : 0u;
+        } else {
+            Zo[0] = (unsigned)(z == 0 ? nz - 1 : z - 1) * PB;
+            Zo[1] = Zc;
+            Zo[2] = (unsigned)(z == nz - 1 ? 0 : z + 1) * PB;
+        }
+        const unsigned ownb = own * ES;
+#pragma unroll
+        for (int a = 0; a < 19; ++a) {
+            const int ex = kE19X[a], ey = kE19Y[a], ez = kE19Z[a];
+            const unsigned inrow = Yo[ey + 1] + Xo[ex + 1];
             if (WALLS) {
-                Zo[0] = z > 0 ? Zc - PB : 0u;
-                Zo[1] = Zc;
-                Zo[2] = z < nz - 1 ? Zc + PB : 0u;
-            } else {
-                Zo[0] = (unsigned)(z == 0 ? nz - 1 : z - 1) * PB;
-                Zo[1] = Zc;
-                Zo[2] = (unsigned)(z == nz - 1 ? 0 : z + 1) * PB;
+                if (ez < 0 && z == 0) {  // Eq. (50): halfway bounce-back
+                    io.store(opposite(a), ownb, (S)fs[a]);
+                    continue;
+                }
+                if (ez > 0 && z == nz - 1) continue;  // leaves through the open top
+                if (ez < 0 && z == nz - 1)             // open top: unknown f copied from below
+                    io.store(a, Zc + inrow, (S)fs[a]);
             }
-            const unsigned ownb = own * ES;
+            io.store(a, Zo[ez + 1] + inrow, (S)fs[a]);
+        }
+        if (P.thermal) {
 #pragma unroll
-            for (int a = 0; a < 19; ++a) {
-                const int ex = kE19X[a], ey = kE19Y[a], ez = kE19Z[a];
-                const unsigned inrow = Yo[ey + 1] + Xo[ex + 1];
+            for (int a = 0; a < 7; ++a) {
+                const int ex = kE7X[a], ey = kE7Y[a], ez = kE7Z[a];
                 if (WALLS) {
-                    if (ez < 0 && z == 0) {  // Eq. (50): halfway bounce-back
-                        stg(A.f_out + opposite(a) * st, ownb, (S)fs[a]);
+                    if (ez < 0 && z == 0) {  // Eq. (51) at the wall
+                        io.store(G0 + opposite(a), ownb, (S)fmad(C(2) * P.wT1, T_bottom, -gp[a]));
                         continue;
                     }
-                    if (ez > 0 && z == nz - 1) continue;  // leaves through the open top
-                    if (ez < 0 && z == nz - 1)             // open top: unknown f copied from below
-                        stg(A.f_out + a * st, Zc + inrow, (S)fs[a]);
-                }
-                stg(A.f_out + a * st, Zo[ez + 1] + inrow, (S)fs[a]);
-            }
-            if (P.thermal) {
-#pragma unroll
-                for (int a = 0; a < 7; ++a) {
-                    const int ex = kE7X[a], ey = kE7Y[a], ez = kE7Z[a];
-                    if (WALLS) {
-                        if (ez < 0 && z == 0) {  // Eq. (51) at the wall
-                            stg(A.g_out + opposite(a) * st, ownb, (S)fmad(C(2) * P.wT1, T_bottom, -gp[a]));
-                            continue;
-                        }
-                        if (ez > 0 && z == nz - 1) {  // Eq. (51) with T_top
-                            stg(A.g_out + opposite(a) * st, ownb, (S)fmad(C(2) * P.wT1, (C)P.T_top, -gp[a]));
-                            continue;
-                        }
+                    if (ez > 0 && z == nz - 1) {  // Eq. (51) with T_top
+                        io.store(G0 + opposite(a), ownb, (S)fmad(C(2) * P.wT1, (C)P.T_top, -gp[a]));
+                        continue;
                     }
-                    stg(A.g_out + a * st, Zo[ez + 1] + Yo[ey + 1] + Xo[ex + 1], (S)gp[a]);
                 }
-            } else {
-#pragma unroll
-                for (int a = 0; a < 7; ++a) stg(A.g_out + a * st, ownb, (S)cg[a]);
+                io.store(G0 + a, Zo[ez + 1] + Yo[ey + 1] + Xo[ex + 1], (S)gp[a]);
             }
-            if (P.gravity) rho_sum += (double)rho;
+        } else {
+#pragma unroll
+            for (int a = 0; a < 7; ++a) io.store(G0 + a, ownb, (S)cg[a]);
+        }
+        if (P.gravity) rho_sum += (double)rho;
+    };
+
+    // Software pipeline over the planes of the chunk.  At iteration z the
+    // populations of plane z (collision) and z+1 (moments) are in registers,
+    // and the loads of plane z+2 are issued right after the moments of z+1 so
+    // that their latency overlaps the barrier and the collision of plane z.
+    // (Issuing them earlier would put more memory operations between a load
+    // and its use than the vmcnt counter can express, which forces a full
+    // drain.)
+    C cf[19], cg[7], c_rho, c_T, c_psi;  // plane z
+    C nf[19], ng[7], nhf[19], nhg[7];    // plane z+1 (tile node, halo node)
+    C qf[19], qg[7], qhf[19], qhg[7];    // plane z+2
+    C n_rho, n_T, n_psi;
+    {
+        C tf[19], tg[7], thf[19], thg[7], t0, t1, t2;
+        C hf0[19], hg0[7];
+        load_plane(z0 - 1, tf, tg, thf, thg);
+        load_plane(z0, cf, cg, hf0, hg0);
+        load_plane(z0 + 1, nf, ng, nhf, nhg);
+        plane_moments(0, tf, tg, thf, thg, t0, t1, t2);
+        plane_moments(1, cf, cg, hf0, hg0, c_rho, c_T, c_psi);
+    }
+    for (int z = z0; z < zend; ++z) {
+        const int s = z - z0 + 1;
+        plane_moments((s + 1) & 3, nf, ng, nhf, nhg, n_rho, n_T, n_psi);
+        if (z + 2 <= zend) load_plane(z + 2, qf, qg, qhf, qhg);
+        __syncthreads();
+        if (active) collide_stream(z, s, cf, cg, c_rho, c_T, c_psi);
+#pragma unroll
+        for (int a = 0; a < 19; ++a) {
+            cf[a] = nf[a];
+            nf[a] = qf[a];
+            nhf[a] = qhf[a];
         }
 #pragma unroll
-        for (int a = 0; a < 19; ++a) cf[a] = nf[a];
-#pragma unroll
-        for (int a = 0; a < 7; ++a) cg[a] = ng[a];
+        for (int a = 0; a < 7; ++a) {
+            cg[a] = ng[a];
+            ng[a] = qg[a];
+            nhg[a] = qhg[a];
+        }
         c_rho = n_rho;
         c_T = n_T;
         c_psi = n_psi;
