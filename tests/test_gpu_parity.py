@@ -111,6 +111,17 @@ def test_pool_boiling_small_fp32():
     _check(e, FP32_TOL, tol_u=tu)
 
 
+def test_pool_boiling_full_size_fp32():
+    """The 256 x 256 x 384 wall workload in its default launch: every node
+    after 2 steps (the second step uses the reduced rho_ave) against the
+    oracle."""
+    w = workload("pool_boiling_256x256x384")
+    _say("pool_boiling_256x256x384 f32 steps=2")
+    e = errors(run_gpu(w, 2, "f32"), run_oracle(w, 2))
+    _say(f"  errors {e}")
+    _check(e, FP32_TOL)
+
+
 def test_thermal_frozen_flat_interface_fp64():
     """thermal = 0 holds the temperature lattice fixed (isothermal runs)."""
     w = workload("flat_interface_128", nx=3, ny=2, nz=64)
