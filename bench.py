@@ -1,7 +1,7 @@
 """Benchmark of the fused D3Q19 + D3Q7 thermal pseudopotential LB step.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                    [--storage f32|f64] [--tile TXxTY] [--chunk CZ] [--no-cpu-baseline]
+                    [--storage f32|f64|f16|bf16|f32dev] [--tile TXxTY] [--chunk CZ] [--no-cpu-baseline]
 
 One step = one fused time step of the whole grid (both lattices, streaming and
 boundary rules) on synthetic seeded input already resident in HBM.  Prints one
@@ -20,9 +20,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS (D3Q19+D3Q7 fused step) + % HBM peak, FP16-store vs FP32 at stated error"
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes per lattice update: 19 + 7 populations and the phi_s
-# history, each read once and written once.
-BYTES_PER_LUP = {"f32": 54 * 4, "f64": 54 * 8}
+# Algorithmic bytes per lattice update: 19 + 7 populations (plus the two
+# reference values rho_r, T_r of the deviation formats) and the FP32 phi_s
+# history (FP64 for f64), each read once and written once.
+BYTES_PER_LUP = {"f32": 2 * 26 * 4 + 8, "f64": 2 * 26 * 8 + 16, "f16": 2 * 28 * 2 + 8, "bf16": 2 * 28 * 2 + 8,
+                 "f32dev": 2 * 28 * 4 + 8}
 KERNEL_SOURCES = ["paper_2201_06039_amd/csrc/lbm_kernels.hpp", "paper_2201_06039_amd/csrc/lbm_api.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_evaporation_128_traffic.json")
 
@@ -78,7 +80,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="evaporation_128")
-    ap.add_argument("--storage", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--storage", default="f32", choices=sorted(BYTES_PER_LUP))
     ap.add_argument("--tile", default=None, help="TXxTY, e.g. 64x4")
     ap.add_argument("--chunk", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")

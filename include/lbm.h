@@ -55,10 +55,24 @@ extern "C" {
 #define LBM_KAPPA_CONST_LAMBDA 0 /* kappa is lambda; chi varies with rho per node */
 #define LBM_KAPPA_CONST_CHI 1    /* kappa is chi itself                           */
 
-/* Storage precision of the populations (arithmetic follows it: F32 storage
- * computes in FP32, F64 storage computes in FP64). */
+/* Storage format of the populations.
+ *   F32, F64: the populations f, g themselves; arithmetic in the same type.
+ *   F16, BF16, F32_DEV: deviations from the rest equilibrium of a per-node
+ *     reference, e = (f_alpha - w_alpha rho_r) s and r = (g_alpha - w_alpha T_r) s,
+ *     with w_alpha the weights of Eq. (5) at u = 0 (1/3, 1/18, 1/36) and of
+ *     the D3Q7 lattice (1 - d, d/6).  rho_r and T_r are the node's density and
+ *     temperature one step earlier, rounded to the storage type and stored as
+ *     two more planes; s = 1024 for F16 (keeps small deviations out of the
+ *     subnormal range), 1 otherwise.  Arithmetic is FP32.  The moments are
+ *     formed from e and the references directly, so the rest part (the O(rho)
+ *     bulk of every population) is never rounded to the storage type: only
+ *     deviations are.  Accuracy of these formats is a property of the
+ *     workload (it is reported against the FP64 evolution, not assumed). */
 #define LBM_STORE_F32 0
 #define LBM_STORE_F64 1
+#define LBM_STORE_F16 2
+#define LBM_STORE_BF16 3
+#define LBM_STORE_F32_DEV 4
 
 /* Problem statement.  Field names are the paper's symbols. */
 typedef struct lbm_params {
@@ -81,14 +95,25 @@ typedef struct lbm_params {
     double T_top;            /* Dirichlet temperature of the open top          */
     int thermal;             /* 1: temperature lattice evolves; 0: held fixed  */
     int storage;             /* LBM_STORE_*                                    */
+    int bc_T_shell;          /* 1: constant-temperature boundary of Sec. IV A:  */
+                             /* the outer layer of nodes (x, y or z at 0 or at */
+                             /* n-1) is a reservoir at T_shell -- it emits     */
+                             /* w T_shell without collision and every g        */
+                             /* streamed into it is replaced by w T_shell, so  */
+                             /* its T is T_shell after every step.  Needs      */
+                             /* bc_z = LBM_BC_PERIODIC and thermal = 1.  The   */
+                             /* density lattice stays periodic.                */
+    double T_shell;          /* reservoir temperature, > 0 when bc_T_shell     */
 } lbm_params;
 
 typedef struct lbm_handle lbm_handle;
 
 /* Device bytes the arena must hold for these parameters (0 if invalid).
- * Layout: two copies of the 19 + 7 population planes (ping-pong), the
- * phi_s history plane, six FP64 staging planes for init and readout, block
- * partial sums and a few scalars, each region 256-byte aligned. */
+ * Layout: two copies (ping-pong) of the 19 + 7 population planes (and, for
+ * the deviation formats, the rho_r and T_r planes), the phi_s history plane
+ * (FP32, FP64 for F64 storage), six FP64 staging planes for init and readout,
+ * block partial sums and a few scalars, each region 256-byte aligned.
+ * 0 also when nx*ny*nz times the element size reaches 2^32 bytes. */
 size_t lbm_arena_bytes(const lbm_params *p);
 
 /* Validate p, derive the constants (T_c from a, b, R as in Sec. IV A; c_sT^2 =
@@ -118,7 +143,9 @@ int lbm_get_rho_u_T(lbm_handle *h, double *rho, double *ux, double *uy, double *
 /* FP64 sums of rho and T over the grid.  Synchronises; may return EUNSTABLE. */
 int lbm_reduce(lbm_handle *h, double *mass, double *energy);
 
-/* Size of the raw checkpoint: header, f, g, phi_s history, rho_ave. */
+/* Size of the raw checkpoint: header, the stored planes (f, g and, for the
+ * deviation formats, rho_r and T_r, in the storage format), phi_s history,
+ * rho_ave. */
 size_t lbm_state_bytes(const lbm_handle *h);
 
 /* Copy the raw state to/from a host buffer of lbm_state_bytes() bytes.
@@ -129,7 +156,7 @@ int lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes);
 
 /* Launch shape of the fused step kernel: an x-y tile of tile_x * tile_y
  * nodes per workgroup marching over chunk_z planes.  Supported tiles:
- * 64x4, 32x8, 64x8, 32x16, 128x4 (FP64 storage: 64x4 and 32x8 only);
+ * 64x4, 32x8, 64x8, 32x16, 128x4 (F64 storage: 64x4 and 32x8 only);
  * chunk_z >= 1 (values above nz are clamped to nz).  EINVAL otherwise.
  * The result of a step does not depend on the launch shape. */
 int lbm_set_launch(lbm_handle *h, int tile_x, int tile_y, int chunk_z);

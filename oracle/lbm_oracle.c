@@ -50,6 +50,8 @@ typedef struct orc_params {
     double patch_radius;   /* radius of the heated patch, centred in x-y */
     double T_top;          /* Dirichlet temperature of the open top */
     int thermal;           /* 1: temperature lattice evolves; 0: held fixed */
+    int bc_T_shell;        /* 1: outer layer of nodes held at T_shell (Sec. IV A) */
+    double T_shell;        /* temperature of that layer */
 } orc_params;
 
 typedef struct orc_sim {
@@ -373,6 +375,14 @@ static void velocity(const orc_sim *s, long i, const double F[3], double u[3]) {
 }
 
 /* Collision of both lattices at every node. */
+/* Constant-temperature boundary of the D^2-law test (Sec. IV A).  Reading:
+ * the outermost layer of nodes of the (otherwise periodic) box is a thermal
+ * reservoir at T_shell; its temperature populations are w T_shell before and
+ * after every collision. */
+static int in_shell(const orc_params *p, int x, int y, int z) {
+    return p->bc_T_shell && (x == 0 || x == p->nx - 1 || y == 0 || y == p->ny - 1 || z == 0 || z == p->nz - 1);
+}
+
 static void pass_collide(orc_sim *s) {
     const orc_params *p = &s->p;
     const long nn = s->nn;
@@ -406,6 +416,13 @@ static void pass_collide(orc_sim *s) {
         }
 
         if (!p->thermal) continue;
+        if (p->bc_T_shell) {
+            const int x = (int)(i % p->nx), y = (int)((i / p->nx) % p->ny), z = (int)(i / ((long)p->nx * p->ny));
+            if (in_shell(p, x, y, z)) {
+                for (int a = 0; a < Q7; ++a) s->gp[a * nn + i] = s->wT[a] * p->T_shell;
+                continue;
+            }
+        }
 
         /* Eq. (48): local velocity divergence from the non-equilibrium part
          * of m_4 (reading: applied at every node, pre-collision m_4). */
@@ -505,6 +522,13 @@ static void pass_stream(orc_sim *s) {
                     s->gn[a * nn + node_index(p, xd, yd, zd)] = s->gp[a * nn + i];
                 }
             }
+    if (p->thermal && p->bc_T_shell) {
+        for (int z = 0; z < p->nz; ++z)
+            for (int y = 0; y < p->ny; ++y)
+                for (int x = 0; x < p->nx; ++x)
+                    if (in_shell(p, x, y, z))
+                        for (int a = 0; a < Q7; ++a) s->gn[a * nn + node_index(p, x, y, z)] = s->wT[a] * p->T_shell;
+    }
     if (walls) {
         const int zt = p->nz - 1;
         for (int y = 0; y < p->ny; ++y)
@@ -540,6 +564,7 @@ int orc_create(const orc_params *p, orc_sim **out) {
     *out = NULL;
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return ORC_EINVAL;
     if (p->bc_z != 0 && p->nz < 3) return ORC_EINVAL;
+    if (p->bc_T_shell && (p->bc_z != 0 || !p->thermal || !(p->T_shell > 0.0))) return ORC_EINVAL;
     if (p->tau_e <= 0.5 || p->tau_v <= 0.5 || p->tau_q <= 0.5 || p->tau_pi <= 0.5) return ORC_EINVAL;
     if (p->vs_q <= 0.5 || p->vs_pi <= 0.5 || p->G == 0.0 || p->cV <= 0.0) return ORC_EINVAL;
     orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));

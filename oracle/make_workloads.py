@@ -33,7 +33,8 @@ A_IVA, A_IVC, B, R, OMEGA = 1.0 / 49.0, 2.0 / 49.0, 2.0 / 21.0, 1.0, 0.344
 # in the D^2 test.  Sec. IV C (nucleate boiling) uses a = 2/49 and chi = 0.08.
 BASE = dict(a=A_IVA, b=B, R=R, acentric=OMEGA, G=-1.0, tau_e=1.25, tau_v=0.8, tau_q=1.0, tau_pi=1.0,
             cV=5.0, d=0.95, kappa_mode=0, kappa=0.2, vs_q=1.0, vs_pi=1.0, grav=[0.0, 0.0, 0.0],
-            T_wall_patch=0.0, T_wall=0.0, patch_radius=0.0, T_top=0.0, thermal=1, bc_z=0)
+            T_wall_patch=0.0, T_wall=0.0, patch_radius=0.0, T_top=0.0, thermal=1, bc_z=0, bc_T_shell=0,
+            T_shell=0.0)
 # Reading: tanh profiles use rho = (l+g)/2 - (l-g)/2 tanh(2 (r-R)/W) with W = 4;
 # W = 2 starts the coupled thermal run with a transient that makes it diverge.
 WIDTH = 4.0
@@ -93,6 +94,17 @@ def main():
              T_v=ca["T"] + 0.14 * TcA, width=WIDTH, noise=1e-4, seed=0),
         10000, "droplet R = 24 at T_sat = 0.86 Tc in vapour at T_sat + 0.14 Tc, 128^3 periodic, "
                "+-1e-4 density noise (seed 0), Sec. IV A parameters")
+    # Sec. IV A D^2 test as stated: 100^3, D_0 = 50, the boundary held at the
+    # vapour temperature (reservoir layer), no noise.  The 48^3 copy with
+    # D_0 = 24 is the size the oracle runs for its D^2-law check and for the
+    # reference values of the storage-format comparisons.
+    for n, r0, steps in ((100, 25.0, 20000), (48, 12.0, 6000)):
+        add(f"d2_law_{n}",
+            dict(nx=n, ny=n, nz=n, bc_T_shell=1, T_shell=ca["T"] + 0.14 * TcA),
+            dict(kind="droplet", radius=r0, rho_l=ca["rho_l"], rho_g=ca["rho_g"], T_l=ca["T"],
+                 T_v=ca["T"] + 0.14 * TcA, width=WIDTH),
+            steps, f"droplet D_0 = {2 * r0:g} at T_sat = 0.86 Tc in vapour at T_sat + 0.14 Tc, {n}^3, outer "
+                   f"layer held at T_sat + 0.14 Tc, Sec. IV A parameters")
     wall = dict(bc_z=1, a=A_IVC, kappa_mode=1, kappa=0.08, grav=[0.0, 0.0, -2e-5], T_wall_patch=0.95 * TcC,
                 T_wall=cc["T"], T_top=cc["T"])
     add("pool_boiling_256x256x384",

@@ -23,16 +23,32 @@ struct TileShape {
 constexpr TileShape kTiles[] = {{64, 4}, {32, 8}, {64, 8}, {32, 16}, {128, 4}};
 
 struct Layout {
-    size_t nn, stride, es, cs;
+    size_t nn, stride, es, cs, planes;
     size_t off_pop[2], off_phi, off_stage, off_part, off_scal, total;
     size_t max_partials;
 };
 
+bool valid_storage(int s) {
+    return s == LBM_STORE_F32 || s == LBM_STORE_F64 || s == LBM_STORE_F16 || s == LBM_STORE_BF16 ||
+           s == LBM_STORE_F32_DEV;
+}
+
+// Bytes of one stored population value.
+size_t element_bytes(int s) {
+    if (s == LBM_STORE_F64) return 8;
+    if (s == LBM_STORE_F16 || s == LBM_STORE_BF16) return 2;
+    return 4;
+}
+
+// Planes per copy: 26 populations, plus rho_r and T_r for the deviation formats.
+size_t planes_of(int s) { return (s == LBM_STORE_F32 || s == LBM_STORE_F64) ? 26 : 28; }
+
 bool valid_params(const lbm_params *p) {
     if (!p) return false;
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return false;
-    // node byte offsets inside a plane set must fit in 32 bits
-    if ((size_t)p->nx * p->ny * p->nz * (p->storage == LBM_STORE_F64 ? 8 : 4) >= (size_t)1 << 32) return false;
+    if (!valid_storage(p->storage)) return false;
+    // node byte offsets inside a plane must fit in 32 bits
+    if ((size_t)p->nx * p->ny * p->nz * element_bytes(p->storage) >= (size_t)1 << 32) return false;
     if (p->bc_z != LBM_BC_PERIODIC && p->bc_z != LBM_BC_WALL_BOTTOM_OPEN_TOP) return false;
     if (p->bc_z == LBM_BC_WALL_BOTTOM_OPEN_TOP && p->nz < 3) return false;
     if (!(p->tau_e > 0.5) || !(p->tau_v > 0.5) || !(p->tau_q > 0.5) || !(p->tau_pi > 0.5)) return false;
@@ -42,8 +58,9 @@ bool valid_params(const lbm_params *p) {
     if (p->kappa_mode != LBM_KAPPA_CONST_LAMBDA && p->kappa_mode != LBM_KAPPA_CONST_CHI) return false;
     if (p->a != 0.0 && !(p->b > 0.0 && p->R > 0.0)) return false;
     if (p->a < 0.0 || p->b < 0.0 || p->R < 0.0) return false;
-    if (p->storage != LBM_STORE_F32 && p->storage != LBM_STORE_F64) return false;
     if (p->thermal != 0 && p->thermal != 1) return false;
+    if (p->bc_T_shell != 0 && p->bc_T_shell != 1) return false;
+    if (p->bc_T_shell && (p->bc_z != LBM_BC_PERIODIC || !p->thermal || !(p->T_shell > 0.0))) return false;
     return true;
 }
 
@@ -61,15 +78,16 @@ size_t max_workgroups(const lbm_params *p) {
 Layout make_layout(const lbm_params *p) {
     Layout L;
     L.nn = (size_t)p->nx * p->ny * p->nz;
-    L.es = p->storage == LBM_STORE_F64 ? 8 : 4;
-    L.cs = L.es;
-    L.stride = align_up(L.nn, 64);
-    // Each ping-pong copy holds its 26 population planes contiguously:
-    // f_0..f_18 then g_0..g_6, `stride` elements apart.
+    L.es = element_bytes(p->storage);
+    L.cs = p->storage == LBM_STORE_F64 ? 8 : 4;
+    L.planes = planes_of(p->storage);
+    L.stride = align_up(L.nn, 128);
+    // Each ping-pong copy holds its planes contiguously, `stride` elements
+    // apart: f_0..f_18, g_0..g_6, then (deviation formats) rho_r and T_r.
     size_t off = 0;
     for (int k = 0; k < 2; ++k) {
         L.off_pop[k] = off;
-        off = align_up(off + 26 * L.stride * L.es, kAlign);
+        off = align_up(off + L.planes * L.stride * L.es, kAlign);
     }
     L.off_phi = off;
     off = align_up(off + L.stride * L.cs, kAlign);
@@ -118,6 +136,8 @@ lbm::Phys<C> make_phys(const lbm_params *p) {
     P.gz = (C)p->g[2];
     P.kappa_mode = p->kappa_mode;
     P.thermal = p->thermal;
+    P.shell = p->bc_T_shell;
+    P.T_shell = (C)p->T_shell;
     P.attract = p->a != 0.0;
     P.gravity = (p->g[0] != 0.0 || p->g[1] != 0.0 || p->g[2] != 0.0);
     P.T_patch = p->T_wall_patch;
@@ -131,9 +151,23 @@ lbm::Phys<C> make_phys(const lbm_params *p) {
 
 struct StateHeader {
     char magic[8];
-    int32_t version, nx, ny, nz, storage, reserved;
+    int32_t version, nx, ny, nz, storage, planes;
     uint64_t nn, es, cs;
 };
+constexpr int32_t kStateVersion = 2;
+
+// Calls fn with a value of the storage-format type of `storage`.
+template <typename Fn>
+int with_format(int storage, Fn &&fn) {
+    switch (storage) {
+    case LBM_STORE_F32: return fn(lbm::StoreF32{});
+    case LBM_STORE_F64: return fn(lbm::StoreF64{});
+    case LBM_STORE_F16: return fn(lbm::StoreF16{});
+    case LBM_STORE_BF16: return fn(lbm::StoreBF16{});
+    case LBM_STORE_F32_DEV: return fn(lbm::StoreF32Dev{});
+    }
+    return LBM_EINVAL;
+}
 
 }  // namespace
 
@@ -152,8 +186,7 @@ struct lbm_handle {
     double *energy() { return (double *)(arena + L.off_scal + 2 * sizeof(double)); }
     double *stage() { return (double *)(arena + L.off_stage); }
     double *partials() { return (double *)(arena + L.off_part); }
-    void *f(int k) { return arena + L.off_pop[k]; }
-    void *g(int k) { return arena + L.off_pop[k] + 19 * L.stride * L.es; }
+    void *pop(int k) { return arena + L.off_pop[k]; }
     void *phi() { return arena + L.off_phi; }
 };
 
@@ -195,40 +228,43 @@ int workgroups_for(const lbm_handle *h, int tx, int ty, int cz) {
     return (int)n;
 }
 
-// The buffer-resource path needs the 26 planes of a copy within 32-bit offsets.
-bool buffer_path(const Layout &L) { return 26 * L.stride * L.es <= 0xFFFFFFFFull; }
+// The buffer-resource path addresses each half of a copy's planes (split at
+// plane 14) with 32-bit offsets.
+bool buffer_path(const Layout &L) { return (size_t)lbm::kSplitPlane * L.stride * L.es <= 0xFFFFFFFFull; }
 
-template <typename S, typename C, int TX, int TY, bool WALLS>
-int launch_step_t(lbm_handle *h, const lbm::StepArgs<S, C> &A, int nb) {
+template <typename ST, int TX, int TY, bool WALLS>
+int launch_step_t(lbm_handle *h, const lbm::StepArgs<ST> &A, int nb) {
     if (buffer_path(h->L))
-        hipLaunchKernelGGL((lbm::k_step<S, C, TX, TY, WALLS, true>), dim3(nb), dim3(TX * TY), 0, h->stream, A);
+        hipLaunchKernelGGL((lbm::k_step<ST, TX, TY, WALLS, true>), dim3(nb), dim3(TX * TY), 0, h->stream, A);
     else
-        hipLaunchKernelGGL((lbm::k_step<S, C, TX, TY, WALLS, false>), dim3(nb), dim3(TX * TY), 0, h->stream, A);
+        hipLaunchKernelGGL((lbm::k_step<ST, TX, TY, WALLS, false>), dim3(nb), dim3(TX * TY), 0, h->stream, A);
     return hip_status(hipGetLastError());
 }
 
-// FP32 instantiates every tile shape; the FP64 build (used to check the
-// kernel against the FP64 oracle) only the two 256-thread tiles, which fit its
-// registers without spilling.
-template <typename S, typename C, bool WALLS>
-int launch_step_tile(lbm_handle *h, const lbm::StepArgs<S, C> &A, int nb) {
+// FP32-arithmetic formats instantiate every tile shape; the FP64 build (used
+// to check the kernel against the FP64 oracle) only the two 256-thread tiles,
+// which fit its registers without spilling.
+template <typename ST, bool WALLS>
+int launch_step_tile(lbm_handle *h, const lbm::StepArgs<ST> &A, int nb) {
     const int tx = h->tile_x, ty = h->tile_y;
-    if (tx == 64 && ty == 4) return launch_step_t<S, C, 64, 4, WALLS>(h, A, nb);
-    if (tx == 32 && ty == 8) return launch_step_t<S, C, 32, 8, WALLS>(h, A, nb);
-    if constexpr (sizeof(C) == 4) {
-        if (tx == 64 && ty == 8) return launch_step_t<S, C, 64, 8, WALLS>(h, A, nb);
-        if (tx == 32 && ty == 16) return launch_step_t<S, C, 32, 16, WALLS>(h, A, nb);
-        if (tx == 128 && ty == 4) return launch_step_t<S, C, 128, 4, WALLS>(h, A, nb);
+    if (tx == 64 && ty == 4) return launch_step_t<ST, 64, 4, WALLS>(h, A, nb);
+    if (tx == 32 && ty == 8) return launch_step_t<ST, 32, 8, WALLS>(h, A, nb);
+    if constexpr (sizeof(typename ST::C) == 4) {
+        if (tx == 64 && ty == 8) return launch_step_t<ST, 64, 8, WALLS>(h, A, nb);
+        if (tx == 32 && ty == 16) return launch_step_t<ST, 32, 16, WALLS>(h, A, nb);
+        if (tx == 128 && ty == 4) return launch_step_t<ST, 128, 4, WALLS>(h, A, nb);
     }
     return LBM_EINVAL;
 }
 
-template <typename S, typename C>
+template <typename ST>
 int step_once(lbm_handle *h) {
-    lbm::StepArgs<S, C> A;
+    using T = typename ST::T;
+    using C = typename ST::C;
+    lbm::StepArgs<ST> A;
     const int c = h->cur, n = 1 - c;
-    A.pop_in = (const S *)h->f(c);
-    A.pop_out = (S *)h->f(n);
+    A.pop_in = (const T *)h->pop(c);
+    A.pop_out = (T *)h->pop(n);
     A.phi = (C *)h->phi();
     A.rho_ave = h->rho_ave();
     A.partials = h->partials();
@@ -242,8 +278,8 @@ int step_once(lbm_handle *h) {
     A.cz = h->chunk_z;
     A.P = make_phys<C>(&h->p);
     const int nb = h->workgroups;
-    int rc = h->p.bc_z == LBM_BC_WALL_BOTTOM_OPEN_TOP ? launch_step_tile<S, C, true>(h, A, nb)
-                                                      : launch_step_tile<S, C, false>(h, A, nb);
+    int rc = h->p.bc_z == LBM_BC_WALL_BOTTOM_OPEN_TOP ? launch_step_tile<ST, true>(h, A, nb)
+                                                      : launch_step_tile<ST, false>(h, A, nb);
     if (rc) return rc;
     if (A.P.gravity) {
         hipLaunchKernelGGL(lbm::k_finish, dim3(1), dim3(256), 0, h->stream, (const double *)h->partials(), nb, 1, 0,
@@ -256,12 +292,13 @@ int step_once(lbm_handle *h) {
 }
 
 // Sum rho and T of the current state into mass/energy (and optionally rho_ave).
-template <typename S>
+template <typename ST>
 int reduce_state(lbm_handle *h, bool set_rho_ave) {
+    using T = typename ST::T;
     const size_t nn = h->L.nn;
     const int nb = (int)((nn + 255) / 256);
-    hipLaunchKernelGGL(lbm::k_sum<S>, dim3(nb), dim3(256), 0, h->stream, (const S *)h->f(h->cur),
-                       (const S *)h->g(h->cur), h->L.stride, nn, h->partials());
+    hipLaunchKernelGGL(lbm::k_sum<ST>, dim3(nb), dim3(256), 0, h->stream, (const T *)h->pop(h->cur), h->L.stride, nn,
+                       h->partials());
     hipLaunchKernelGGL(lbm::k_finish, dim3(1), dim3(256), 0, h->stream, (const double *)h->partials(), nb, 2, 0, 1.0,
                        h->mass());
     hipLaunchKernelGGL(lbm::k_finish, dim3(1), dim3(256), 0, h->stream, (const double *)h->partials(), nb, 2, 1, 1.0,
@@ -334,15 +371,12 @@ int lbm_init_fields(lbm_handle *h, const double *rho, const double *ux, const do
     const lbm::Phys<double> P = make_phys<double>(&h->p);
     const int nb = (int)((nn + 255) / 256);
     h->cur = 0;
-    if (h->p.storage == LBM_STORE_F64) {
-        hipLaunchKernelGGL((lbm::k_init<double, double>), dim3(nb), dim3(256), 0, h->stream, (const double *)st, nn,
-                           (double *)h->f(0), (double *)h->g(0), (double *)h->phi(), h->L.stride, P, h->status());
-        rc = reduce_state<double>(h, true);
-    } else {
-        hipLaunchKernelGGL((lbm::k_init<float, float>), dim3(nb), dim3(256), 0, h->stream, (const double *)st, nn,
-                           (float *)h->f(0), (float *)h->g(0), (float *)h->phi(), h->L.stride, P, h->status());
-        rc = reduce_state<float>(h, true);
-    }
+    rc = with_format(h->p.storage, [&](auto fmt) {
+        using ST = decltype(fmt);
+        hipLaunchKernelGGL(lbm::k_init<ST>, dim3(nb), dim3(256), 0, h->stream, (const double *)st, nn,
+                           (typename ST::T *)h->pop(0), (typename ST::C *)h->phi(), h->L.stride, P, h->status());
+        return reduce_state<ST>(h, true);
+    });
     if (rc) return rc;
     unsigned s = 0;
     rc = check_status(h, &s);
@@ -360,7 +394,7 @@ int lbm_step(lbm_handle *h, int n) {
     if (!h || n < 0) return LBM_EINVAL;
     if (!h->initialized) return LBM_ESTATE;
     for (int k = 0; k < n; ++k) {
-        const int rc = h->p.storage == LBM_STORE_F64 ? step_once<double, double>(h) : step_once<float, float>(h);
+        const int rc = with_format(h->p.storage, [&](auto fmt) { return step_once<decltype(fmt)>(h); });
         if (rc) return rc;
     }
     return LBM_OK;
@@ -374,18 +408,15 @@ int lbm_get_rho_u_T(lbm_handle *h, double *rho, double *ux, double *uy, double *
     const lbm::Phys<double> P = make_phys<double>(&h->p);
     double *st = h->stage();
     const int walls = h->p.bc_z == LBM_BC_WALL_BOTTOM_OPEN_TOP;
-    if (h->p.storage == LBM_STORE_F64) {
-        hipLaunchKernelGGL(lbm::k_macro<double>, dim3(nb), dim3(256), 0, h->stream, (const double *)h->f(h->cur),
-                           (const double *)h->g(h->cur), h->L.stride, nn, P, st);
-        hipLaunchKernelGGL(lbm::k_velocity<double>, dim3(nb), dim3(256), 0, h->stream, (const double *)h->f(h->cur),
-                           h->L.stride, h->p.nx, h->p.ny, h->p.nz, walls, P, (const double *)h->rho_ave(), st);
-    } else {
-        hipLaunchKernelGGL(lbm::k_macro<float>, dim3(nb), dim3(256), 0, h->stream, (const float *)h->f(h->cur),
-                           (const float *)h->g(h->cur), h->L.stride, nn, P, st);
-        hipLaunchKernelGGL(lbm::k_velocity<float>, dim3(nb), dim3(256), 0, h->stream, (const float *)h->f(h->cur),
-                           h->L.stride, h->p.nx, h->p.ny, h->p.nz, walls, P, (const double *)h->rho_ave(), st);
-    }
-    if (hipGetLastError() != hipSuccess) return LBM_EHIP;
+    const int lrc = with_format(h->p.storage, [&](auto fmt) {
+        using ST = decltype(fmt);
+        const typename ST::T *pop = (const typename ST::T *)h->pop(h->cur);
+        hipLaunchKernelGGL(lbm::k_macro<ST>, dim3(nb), dim3(256), 0, h->stream, pop, h->L.stride, nn, P, st);
+        hipLaunchKernelGGL(lbm::k_velocity<ST>, dim3(nb), dim3(256), 0, h->stream, pop, h->L.stride, h->p.nx, h->p.ny,
+                           h->p.nz, walls, P, (const double *)h->rho_ave(), st);
+        return hip_status(hipGetLastError());
+    });
+    if (lrc) return lrc;
     double *dst[5] = {rho, ux, uy, uz, T};
     for (int k = 0; k < 5; ++k) {
         if (hipMemcpyAsync(dst[k], st + k * nn, nn * sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess)
@@ -404,7 +435,7 @@ int lbm_get_rho_u_T(lbm_handle *h, double *rho, double *ux, double *uy, double *
 int lbm_reduce(lbm_handle *h, double *mass, double *energy) {
     if (!h || !mass || !energy) return LBM_EINVAL;
     if (!h->initialized) return LBM_ESTATE;
-    int rc = h->p.storage == LBM_STORE_F64 ? reduce_state<double>(h, false) : reduce_state<float>(h, false);
+    int rc = with_format(h->p.storage, [&](auto fmt) { return reduce_state<decltype(fmt)>(h, false); });
     if (rc) return rc;
     double me[2];
     if (hipMemcpyAsync(me, h->mass(), 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess)
@@ -424,7 +455,7 @@ int lbm_reduce(lbm_handle *h, double *mass, double *energy) {
 size_t lbm_state_bytes(const lbm_handle *h) {
     if (!h) return 0;
     const size_t nn = h->L.nn;
-    return sizeof(StateHeader) + 26 * nn * h->L.es + nn * h->L.cs + sizeof(double);
+    return sizeof(StateHeader) + h->L.planes * nn * h->L.es + nn * h->L.cs + sizeof(double);
 }
 
 int lbm_get_state(lbm_handle *h, void *host_buf, size_t bytes) {
@@ -433,7 +464,8 @@ int lbm_get_state(lbm_handle *h, void *host_buf, size_t bytes) {
     StateHeader hd;
     memset(&hd, 0, sizeof(hd));
     memcpy(hd.magic, "LBMSTAT1", 8);
-    hd.version = 1;
+    hd.version = kStateVersion;
+    hd.planes = (int32_t)h->L.planes;
     hd.nx = h->p.nx;
     hd.ny = h->p.ny;
     hd.nz = h->p.nz;
@@ -445,12 +477,8 @@ int lbm_get_state(lbm_handle *h, void *host_buf, size_t bytes) {
     memcpy(out, &hd, sizeof(hd));
     out += sizeof(hd);
     const size_t plane = h->L.nn * h->L.es;
-    for (int a = 0; a < 19; ++a, out += plane)
-        if (hipMemcpyAsync(out, (char *)h->f(h->cur) + a * h->L.stride * h->L.es, plane, hipMemcpyDeviceToHost,
-                           h->stream) != hipSuccess)
-            return LBM_EHIP;
-    for (int a = 0; a < 7; ++a, out += plane)
-        if (hipMemcpyAsync(out, (char *)h->g(h->cur) + a * h->L.stride * h->L.es, plane, hipMemcpyDeviceToHost,
+    for (size_t a = 0; a < h->L.planes; ++a, out += plane)
+        if (hipMemcpyAsync(out, (char *)h->pop(h->cur) + a * h->L.stride * h->L.es, plane, hipMemcpyDeviceToHost,
                            h->stream) != hipSuccess)
             return LBM_EHIP;
     if (hipMemcpyAsync(out, h->phi(), h->L.nn * h->L.cs, hipMemcpyDeviceToHost, h->stream) != hipSuccess)
@@ -472,19 +500,16 @@ int lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes) {
     if (!h || !host_buf || bytes != lbm_state_bytes(h)) return LBM_EINVAL;
     StateHeader hd;
     memcpy(&hd, host_buf, sizeof(hd));
-    if (memcmp(hd.magic, "LBMSTAT1", 8) != 0 || hd.version != 1 || hd.nx != h->p.nx || hd.ny != h->p.ny ||
-        hd.nz != h->p.nz || hd.storage != h->p.storage || hd.nn != h->L.nn || hd.es != h->L.es || hd.cs != h->L.cs)
+    if (memcmp(hd.magic, "LBMSTAT1", 8) != 0 || hd.version != kStateVersion || hd.nx != h->p.nx ||
+        hd.ny != h->p.ny || hd.nz != h->p.nz || hd.storage != h->p.storage || hd.planes != (int32_t)h->L.planes ||
+        hd.nn != h->L.nn || hd.es != h->L.es || hd.cs != h->L.cs)
         return LBM_EINVAL;
     const char *in = (const char *)host_buf + sizeof(hd);
     const size_t plane = h->L.nn * h->L.es;
     h->cur = 0;
-    for (int a = 0; a < 19; ++a, in += plane)
-        if (hipMemcpyAsync((char *)h->f(0) + a * h->L.stride * h->L.es, in, plane, hipMemcpyHostToDevice, h->stream) !=
-            hipSuccess)
-            return LBM_EHIP;
-    for (int a = 0; a < 7; ++a, in += plane)
-        if (hipMemcpyAsync((char *)h->g(0) + a * h->L.stride * h->L.es, in, plane, hipMemcpyHostToDevice, h->stream) !=
-            hipSuccess)
+    for (size_t a = 0; a < h->L.planes; ++a, in += plane)
+        if (hipMemcpyAsync((char *)h->pop(0) + a * h->L.stride * h->L.es, in, plane, hipMemcpyHostToDevice,
+                           h->stream) != hipSuccess)
             return LBM_EHIP;
     if (hipMemcpyAsync(h->phi(), in, h->L.nn * h->L.cs, hipMemcpyHostToDevice, h->stream) != hipSuccess)
         return LBM_EHIP;

@@ -1,13 +1,21 @@
 // Device code of liblbm for gfx950 (MI355X): the fused D3Q19 + D3Q7 time step
 // of Li, Yu & Luo (arXiv:2201.06039) and its helper kernels.
 //
-// State layout in HBM (structure of arrays, x fastest):
-//   f[alpha][z][y][x], alpha = 0..18   post-streaming D3Q19 populations at t
-//   g[alpha][z][y][x], alpha = 0..6    post-streaming D3Q7 populations at t
-//   phi[z][y][x]                       phi_s(x, t - dt), Eq. (23) history
-// Two copies of f and g ping-pong between steps (push streaming: a node
-// reads its own populations and writes the post-collision values to its
-// neighbours in the other copy).
+// State layout in HBM (structure of arrays, x fastest), two ping-pong copies:
+//   plane  0..18   D3Q19 populations f_alpha at time t (post-streaming)
+//   plane 19..25   D3Q7 populations g_alpha
+//   plane 26, 27   (deviation storage only) per-node references rho_r, T_r
+// plus one phi_s(t - dt) plane (Eq. (23) history) updated in place.
+//
+// Storage formats.  Plain FP32/FP64 store the populations themselves.  The
+// deviation formats (FP16, BF16, and FP32 for comparison) store
+//   e_alpha = (f_alpha - w_alpha rho_r) * scale,   r_alpha = (g_alpha - w_alpha T_r) * scale
+// where rho_r, T_r are the density and temperature of the node one step
+// earlier rounded to the storage type, written by the node itself.  A node's
+// moments are formed from e and the reference directly (rho = rho_r + sum e,
+// rho u = sum e_alpha e_alpha), so the O(rho) rest part never enters a
+// rounded difference.  Push streaming writes the value for node y encoded
+// against y's new reference, which the writer reads from the LDS ring.
 //
 // The fused step kernel assigns each workgroup an x-y tile of TX*TY nodes and
 // a chunk of z planes.  It marches up the chunk: for plane z+1 it computes
@@ -15,7 +23,7 @@
 // the 18-neighbour force of Eq. (7) and the density gradient at plane z read
 // same-time-level values from LDS.  Halo nodes are recomputed from their own
 // populations (an extra read served mostly by L2), which keeps the whole step
-// in one launch with 27 reads and 27 writes of state per node.
+// in one launch with one read and one write of the state per node.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -33,6 +41,9 @@ constexpr int kE7Y[7] = {0, 0, 0, 1, -1, 0, 0};
 constexpr int kE7Z[7] = {0, 0, 0, 0, 0, 1, -1};
 
 __host__ __device__ constexpr int opposite(int a) { return a == 0 ? 0 : ((a & 1) ? a + 1 : a - 1); }
+
+// Rest weights of the D3Q19 equilibrium: w0 = 1/3, axis 1/18, diagonal 1/36.
+__host__ __device__ constexpr double w19(int a) { return a == 0 ? 1.0 / 3.0 : (a < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
 
 template <typename C>
 struct Num;
@@ -66,6 +77,8 @@ struct Phys {
     C gx, gy, gz;         // gravity
     int kappa_mode;       // 0: constant lambda, 1: constant chi
     int thermal;          // temperature lattice evolves
+    int shell;            // outer layer of nodes held at T_shell (periodic grids only)
+    C T_shell;
     int attract;          // a != 0
     int gravity;          // g != 0
     double T_patch, T_wall, patch_r2, T_top, cx, cy;  // walls (decisions in FP64)
@@ -210,18 +223,159 @@ __device__ __forceinline__ void equilibrium19(C rho, C ux, C uy, C uz, C *meq) {
     meq[18] = varphi + rho * cs2 * (uy2 + uz2);
 }
 
-template <typename S, typename C>
+// a * b + c rounded once (the library is built without automatic contraction,
+// so every fused operation is one of these and the rounding is fixed).
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// ---------------------------------------------------------------------------
+// Storage formats of the populations.
+// ---------------------------------------------------------------------------
+
+// Each format: T = stored element, C = compute type, kDev = deviation
+// encoding with references, kScale = factor applied to stored deviations
+// (keeps FP16 deviations above the subnormal range).  dec/enc map stored
+// deviations (or raw populations) to C and back; rdec/renc do the same for
+// the unscaled references.
+struct StoreF32 {
+    using T = float;
+    using C = float;
+    static constexpr bool kDev = false;
+    __device__ static C dec(T v) { return v; }
+    __device__ static T enc(C v) { return v; }
+    __device__ static C rdec(T v) { return v; }
+    __device__ static T renc(C v) { return v; }
+    __device__ static double ddec(T v) { return v; }
+    __device__ static T denc(double v) { return (T)v; }
+};
+struct StoreF64 {
+    using T = double;
+    using C = double;
+    static constexpr bool kDev = false;
+    __device__ static C dec(T v) { return v; }
+    __device__ static T enc(C v) { return v; }
+    __device__ static C rdec(T v) { return v; }
+    __device__ static T renc(C v) { return v; }
+    __device__ static double ddec(T v) { return v; }
+    __device__ static T denc(double v) { return v; }
+};
+struct StoreF32Dev {
+    using T = float;
+    using C = float;
+    static constexpr bool kDev = true;
+    __device__ static C dec(T v) { return v; }
+    __device__ static T enc(C v) { return v; }
+    __device__ static C rdec(T v) { return v; }
+    __device__ static T renc(C v) { return v; }
+    __device__ static double ddec(T v) { return v; }
+    __device__ static T denc(double v) { return (T)v; }
+};
+struct StoreF16 {
+    using T = _Float16;
+    using C = float;
+    static constexpr bool kDev = true;
+    static constexpr float kScale = 1024.0f, kInv = 1.0f / 1024.0f;
+    __device__ static C dec(T v) { return (float)v * kInv; }
+    __device__ static T enc(C v) { return (T)(v * kScale); }
+    __device__ static C rdec(T v) { return (float)v; }
+    __device__ static T renc(C v) { return (T)v; }
+    __device__ static double ddec(T v) { return (double)(float)v * (1.0 / 1024.0); }
+    __device__ static T denc(double v) { return (T)(float)(v * 1024.0); }
+};
+struct StoreBF16 {  // conversions round to nearest even (v_cvt_pk_bf16_f32 on gfx950)
+    using T = __bf16;
+    using C = float;
+    static constexpr bool kDev = true;
+    __device__ static C dec(T v) { return (float)v; }
+    __device__ static T enc(C v) { return (T)v; }
+    __device__ static C rdec(T v) { return (float)v; }
+    __device__ static T renc(C v) { return (T)v; }
+    __device__ static double ddec(T v) { return (double)(float)v; }
+    __device__ static T denc(double v) { return (T)(float)v; }
+};
+
+template <typename ST>
+constexpr int planes_of() { return ST::kDev ? 28 : 26; }
+
+// Loads/stores of a 2-, 4- or 8-byte element through a buffer resource.
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+    if constexpr (sizeof(T) == 2) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
+    else if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
+    else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
+}
+template <typename T>
+__device__ __forceinline__ void buf_st(T x, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+    if constexpr (sizeof(T) == 2) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, v, s, 0);
+    } else if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v, s, 0);
+    } else {
+        typedef unsigned v2u __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, x), r, v, s, 0);
+    }
+}
+
+constexpr int kBufferFlags = 0x00020000;  // raw dword buffer; the record count is left at its maximum and
+                                          // every offset is kept inside the planes by construction
+constexpr int kSplitPlane = 14;           // planes [0,14) and [14,28) sit behind two resources
+
+// Access to the population planes of the two ping-pong copies.
+//  BUF = true: two buffer resources per copy (planes below and from plane 14);
+//  a plane's offset is a scalar and the node's byte offset one 32-bit vector
+//  offset shared by all planes, so loads cost no vector address arithmetic.
+//  Needs 14 planes to span less than 4 GiB.
+//  BUF = false: plain global pointers (any size).
+template <typename T, bool BUF>
+struct PopIO;
+
+template <typename T>
+struct PopIO<T, true> {
+    __amdgpu_buffer_rsrc_t in_lo, in_hi, out_lo, out_hi;
+    unsigned sb;  // plane stride in bytes
+    __device__ PopIO(const T *pin, T *pout, size_t stride) {
+        sb = (unsigned)(stride * sizeof(T));
+        in_lo = __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(pin), 0, -1, kBufferFlags);
+        in_hi = __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(pin) + kSplitPlane * stride, 0, -1, kBufferFlags);
+        out_lo = __builtin_amdgcn_make_buffer_rsrc(pout, 0, -1, kBufferFlags);
+        out_hi = __builtin_amdgcn_make_buffer_rsrc(pout + kSplitPlane * stride, 0, -1, kBufferFlags);
+    }
+    __device__ T load(int a, unsigned boff) const {
+        return a < kSplitPlane ? buf_ld<T>(in_lo, boff, (unsigned)a * sb)
+                               : buf_ld<T>(in_hi, boff, (unsigned)(a - kSplitPlane) * sb);
+    }
+    __device__ void store(int a, unsigned boff, T v) const {
+        if (a < kSplitPlane) buf_st<T>(v, out_lo, boff, (unsigned)a * sb);
+        else buf_st<T>(v, out_hi, boff, (unsigned)(a - kSplitPlane) * sb);
+    }
+};
+
+template <typename T>
+struct PopIO<T, false> {
+    const T *in;
+    T *out;
+    size_t st;
+    __device__ PopIO(const T *pin, T *pout, size_t stride) : in(pin), out(pout), st(stride) {}
+    __device__ T load(int a, unsigned boff) const {
+        return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(in + a * st) + boff);
+    }
+    __device__ void store(int a, unsigned boff, T v) const {
+        *reinterpret_cast<T *>(reinterpret_cast<char *>(out + a * st) + boff) = v;
+    }
+};
+
+template <typename ST>
 struct StepArgs {
-    const S *__restrict__ pop_in;   // 26 planes: f_0..f_18, g_0..g_6, `stride` elements apart
-    S *__restrict__ pop_out;
-    C *__restrict__ phi;
+    const typename ST::T *__restrict__ pop_in;  // planes of the current state, `stride` elements apart
+    typename ST::T *__restrict__ pop_out;
+    typename ST::C *__restrict__ phi;
     const double *__restrict__ rho_ave;
     double *__restrict__ partials;  // per-workgroup sum of rho (when gravity is on)
     unsigned *__restrict__ status;
     size_t stride;                  // elements between population planes
     int nx, ny, nz;
     int ntx, nty, cz;               // tiles in x, y; planes per chunk
-    Phys<C> P;
+    Phys<typename ST::C> P;
 };
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
@@ -232,86 +386,31 @@ __device__ __forceinline__ int xcd_logical_block(int b, int nb) {
     return xcd * q + (xcd < r ? xcd : r) + (b >> 3);
 }
 
-// a * b + c rounded once (the library is built without automatic contraction,
-// so every fused operation is one of these and the rounding is fixed).
-__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-// Access to the 26 population planes of the two ping-pong copies.
-//  BUF = true: one buffer resource per copy; a population access is
-//  `plane * stride_bytes` (a scalar offset) + the node's byte offset (a 32-bit
-//  vector offset shared by all 26 planes), so no vector address arithmetic is
-//  spent on loads.  Needs the 26 planes of a copy to span less than 4 GiB.
-//  BUF = false: plain global pointers (any size).
-template <typename S, bool BUF>
-struct PopIO;
-
-template <typename S>
-struct BufBits;
-template <>
-struct BufBits<float> {
-    __device__ static float ld(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
-    }
-    __device__ static void st(float x, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v, s, 0);
-    }
-};
-template <>
-struct BufBits<double> {
-    __device__ static double ld(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
-        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
-    }
-    __device__ static void st(double x, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
-        typedef unsigned v2u __attribute__((ext_vector_type(2)));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, x), r, v, s, 0);
-    }
+// One node's loaded state: e = stored populations decoded to C (deviations
+// for the deviation formats), br/bt = references (0 for plain storage).
+template <typename C>
+struct NodePops {
+    C e[19], r[7], br, bt;
 };
 
-constexpr int kBufferFlags = 0x00020000;  // raw dword buffer; the record count is left at its maximum and
-                                          // every offset is kept inside the 26 planes by construction
-
-template <typename S>
-struct PopIO<S, true> {
-    __amdgpu_buffer_rsrc_t in, out;
-    unsigned sb;  // plane stride in bytes
-    __device__ PopIO(const S *pin, S *pout, size_t stride) {
-        sb = (unsigned)(stride * sizeof(S));
-        in = __builtin_amdgcn_make_buffer_rsrc(const_cast<S *>(pin), 0, -1, kBufferFlags);
-        out = __builtin_amdgcn_make_buffer_rsrc(pout, 0, -1, kBufferFlags);
-    }
-    __device__ S load(int a, unsigned boff) const { return BufBits<S>::ld(in, boff, (unsigned)a * sb); }
-    __device__ void store(int a, unsigned boff, S v) const { BufBits<S>::st(v, out, boff, (unsigned)a * sb); }
-};
-
-template <typename S>
-struct PopIO<S, false> {
-    const S *in;
-    S *out;
-    size_t st;
-    __device__ PopIO(const S *pin, S *pout, size_t stride) : in(pin), out(pout), st(stride) {}
-    __device__ S load(int a, unsigned boff) const {
-        return *reinterpret_cast<const S *>(reinterpret_cast<const char *>(in + a * st) + boff);
-    }
-    __device__ void store(int a, unsigned boff, S v) const {
-        *reinterpret_cast<S *>(reinterpret_cast<char *>(out + a * st) + boff) = v;
-    }
-};
-
-template <typename S, typename C, int TX, int TY, bool WALLS, bool BUF>
-__global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<S, C> A) {
+template <typename ST, int TX, int TY, bool WALLS, bool BUF>
+__global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
+    using E = typename ST::T;  // stored element
+    using C = typename ST::C;
+    constexpr bool DEV = ST::kDev;
     constexpr int NT = TX * TY, EX = TX + 2, EY = TY + 2, NE = EX * EY, NH = NE - NT;
     static_assert(NH <= NT, "halo must not exceed the tile");
-    constexpr unsigned ES = sizeof(S);
-    constexpr int G0 = 19;  // first D3Q7 plane
+    constexpr unsigned ES = sizeof(E);
+    constexpr int G0 = 19, RRHO = 26, RT = 27;  // first D3Q7 plane, reference planes
     __shared__ C s_psi[4][NE];
     __shared__ C s_rho[4][NE];
+    __shared__ C s_tem[DEV ? 4 : 1][DEV ? NE : 1];
     __shared__ double s_red[NT / 64];
 
     const Phys<C> &P = A.P;
     const int nx = A.nx, ny = A.ny, nz = A.nz;
     const unsigned plane = (unsigned)nx * (unsigned)ny;
-    const PopIO<S, BUF> io(A.pop_in, A.pop_out, A.stride);
+    const PopIO<E, BUF> io(A.pop_in, A.pop_out, A.stride);
 
     const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
     const int itx = logical % A.ntx;
@@ -352,28 +451,29 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<S, C> A) {
         return zz < 0 ? zz + nz : zz;
     };
 
-    // Populations of plane zp for this thread's tile node (kf, kg) and its
-    // halo node (hf, hg).
-    auto load_plane = [&](int zp, C *kf, C *kg, C *hf, C *hg) {
-        const unsigned zoff = (unsigned)zmap(zp) * plane;
-        const unsigned ib = (zoff + irow) * ES;
+    auto load_node = [&](unsigned b, NodePops<C> &n) {
 #pragma unroll
-        for (int a = 0; a < 19; ++a) kf[a] = (C)io.load(a, ib);
+        for (int a = 0; a < 19; ++a) n.e[a] = ST::dec(io.load(a, b));
 #pragma unroll
-        for (int a = 0; a < 7; ++a) kg[a] = (C)io.load(G0 + a, ib);
-        if (has_halo) {
-            const unsigned hb = (zoff + hrow) * ES;
-#pragma unroll
-            for (int a = 0; a < 19; ++a) hf[a] = (C)io.load(a, hb);
-#pragma unroll
-            for (int a = 0; a < 7; ++a) hg[a] = (C)io.load(G0 + a, hb);
+        for (int a = 0; a < 7; ++a) n.r[a] = ST::dec(io.load(G0 + a, b));
+        if constexpr (DEV) {
+            n.br = ST::rdec(io.load(RRHO, b));
+            n.bt = ST::rdec(io.load(RT, b));
+        } else {
+            n.br = C(0);
+            n.bt = C(0);
         }
+    };
+    // State of plane zp for this thread's tile node and its halo node.
+    auto load_plane = [&](int zp, NodePops<C> &k, NodePops<C> &h) {
+        const unsigned zoff = (unsigned)zmap(zp) * plane;
+        load_node((zoff + irow) * ES, k);
+        if (has_halo) load_node((zoff + hrow) * ES, h);
     };
 
     // rho, T, psi of a loaded plane (tile node and halo node) -> LDS slot.
-    auto plane_moments = [&](int slot, const C *kf, const C *kg, const C *hf, const C *hg, C &krho, C &kT,
-                             C &kpsi) {
-        const C rho = sum19(kf), T = sum7(kg);
+    auto plane_moments = [&](int slot, const NodePops<C> &k, const NodePops<C> &h, C &krho, C &kT, C &kpsi) {
+        const C rho = k.br + sum19(k.e), T = k.bt + sum7(k.r);
         const C p2 = psi_squared(P, rho, T);
         // Unstable node (rho <= 0, psi^2 < 0 or NaN): one flag update per wave.
         const bool bad = active && (!(rho > C(0)) || !(p2 >= C(0)));
@@ -382,14 +482,16 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<S, C> A) {
         const C psi = Num<C>::sqrt(p2 > C(0) ? p2 : C(0));
         s_psi[slot][li] = psi;
         s_rho[slot][li] = rho;
+        if constexpr (DEV) s_tem[slot][li] = T;
         krho = rho;
         kT = T;
         kpsi = psi;
         if (has_halo) {
-            const C hr = sum19(hf), hT = sum7(hg);
+            const C hr = h.br + sum19(h.e), hT = h.bt + sum7(h.r);
             const C hp2 = psi_squared(P, hr, hT);
             s_psi[slot][hli] = Num<C>::sqrt(hp2 > C(0) ? hp2 : C(0));
             s_rho[slot][hli] = hr;
+            if constexpr (DEV) s_tem[slot][hli] = hT;
         }
     };
 
@@ -408,8 +510,9 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<S, C> A) {
 
     // Collision and streaming of the tile node at plane z (slot s of the ring
     // holds plane z; s-1 and s+1 its neighbours).
-    auto collide_stream = [&](int z, int s, const C *cf, const C *cg, C rho, C T, C psi) {
+    auto collide_stream = [&](int z, int s, const NodePops<C> &nd, C rho, C T, C psi) {
         const int sm = (s + 3) & 3, s0 = s & 3, sp = (s + 1) & 3;
+        const int sl[3] = {sm, s0, sp};
         // Eq. (7) and the isotropic gradient: omega(1) = 1/6, omega(2) = 1/12.
 #define NB(arr, sl, dx, dy) arr[sl][li + (dy) * EX + (dx)]
 #define STENCIL(arr, OX, OY, OZ)                                                                                    \
@@ -436,12 +539,14 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<S, C> A) {
             Fy = fmad(drho, P.gy, Fy);
             Fz = fmad(drho, P.gz, Fz);
         }
-        // Moments as deviations from the rest equilibrium w rho: the rest
+        // Moments as deviations from the rest equilibrium w rho.  The rest
         // part is conserved by the collision (Lambda_0 = 1, S_0 = 0, and
         // m_eq(rho, 0) relaxes onto itself), so it is added back to f* at the
-        // end instead of being carried through O(rho) sums.
+        // end instead of being carried through O(rho) sums.  With e the
+        // stored values (f - w rho_r), rho - rho_r = sum e plays the role of
+        // rho in the rest-part subtraction.
         C m[19];
-        moments19<C, true>(cf, m, rho);
+        moments19<C, true>(nd.e, m, rho - nd.br);
         // Eq. (10)
         const C ux = fmad(C(0.5), Fx, m[1]) * inv_rho;
         const C uy = fmad(C(0.5), Fy, m[2]) * inv_rho;
@@ -498,29 +603,40 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<S, C> A) {
         ms[16] = fmad(P.lam_pi, meq[16] - m[16], fmad(hp, xFx + yFy, m[16]));
         ms[17] = fmad(P.lam_pi, meq[17] - m[17], fmad(hp, xFx + zFz, m[17]));
         ms[18] = fmad(P.lam_pi, meq[18] - m[18], fmad(hp, yFy + zFz, m[18]));
-        C fs[19];
+        C fs[19];  // f* - w rho
         populations19(ms, fs);
-        {
-            // rest part w rho; r0 closes the sum exactly, since the rounded
-            // weights 1/3 + 6/18 + 12/36 do not add up to 1.
-            const C r1 = rho * C(1.0 / 18.0), r2 = rho * C(1.0 / 36.0);
-            const C r0 = rho - fmad(C(6), r1, C(12) * r2);
-            fs[0] += r0;
-#pragma unroll
-            for (int a = 1; a < 7; ++a) fs[a] += r1;
-#pragma unroll
-            for (int a = 7; a < 19; ++a) fs[a] += r2;
-        }
 
         // ---- D3Q7 thermal lattice ----
-        C gp[7];
+        C gs[7];  // g+ - w T_emit
         const unsigned own = (unsigned)z * plane + irow;
-        if (P.thermal) {
+        // Constant-temperature boundary (Sec. IV A): the outer layer of nodes
+        // is a reservoir at T_shell.  It emits w T_shell without collision,
+        // and every population streamed into it is replaced by w T_shell.
+        bool xs[3] = {false, false, false}, ys[3] = {false, false, false}, zs[3] = {false, false, false};
+        bool own_shell = false;
+        if (!WALLS && P.shell) {
+            const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+            xs[0] = xm == 0 || xm == nx - 1;
+            xs[1] = xw == 0 || xw == nx - 1;
+            xs[2] = xp == 0 || xp == nx - 1;
+            ys[0] = ym == 0 || ym == ny - 1;
+            ys[1] = yw == 0 || yw == ny - 1;
+            ys[2] = yp == 0 || yp == ny - 1;
+            zs[0] = zm == 0 || zm == nz - 1;
+            zs[1] = z == 0 || z == nz - 1;
+            zs[2] = zp == 0 || zp == nz - 1;
+            own_shell = xs[1] || ys[1] || zs[1];
+        }
+        const C T_emit = own_shell ? P.T_shell : T;
+        if (own_shell) {
+#pragma unroll
+            for (int a = 0; a < 7; ++a) gs[a] = C(0);
+        } else if (P.thermal) {
             // Eq. (48): local velocity divergence (pre-collision m_4).
             const C divu = fmad(P.divu_b, S4, -fmad(P.divu_a, m[4] - meq[4], C(2) * Fu)) * (C(1.5) * inv_rho);
-            // Eq. (38): n = N g
-            const C n1 = cg[1] - cg[2], n2 = cg[3] - cg[4], n3 = cg[5] - cg[6];
-            const C a12 = cg[1] + cg[2], a34 = cg[3] + cg[4], a56 = cg[5] + cg[6];
+            // Eq. (38): n = N g (the reference part w T_r cancels from n1..n3, n5, n6)
+            const C n1 = nd.r[1] - nd.r[2], n2 = nd.r[3] - nd.r[4], n3 = nd.r[5] - nd.r[6];
+            const C a12 = nd.r[1] + nd.r[2], a34 = nd.r[3] + nd.r[4], a56 = nd.r[5] + nd.r[6];
             const C n5 = a12 - a34, n6 = a12 - a56;
             const C chi = P.kappa_mode ? P.kappa : P.kappa * inv_rho * P.inv_cV;
             const C inv_vsT = Num<C>::rcp(fmad(chi, P.inv_csT2, C(0.5)));
@@ -532,26 +648,25 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<S, C> A) {
             const C adv = fmad(fmad(cr, grx, -ux), dTx, fmad(fmad(cr, gry, -uy), dTy, fmad(cr, grz, -uz) * dTz));
             const C phis = fmad(-T * P.R * P.inv_cV, Num<C>::rcp(fmad(-P.b, rho, C(1))) * divu, adv);
             // Eq. (39) with Eq. (42)-(43); n4 is carried as its deviation
-            // n4 - d T = (1 - d) T - g0 from the equilibrium.
+            // n4 - d T = (1 - d) T - g0 = w0 (T - T_r) - (g0 - w0 T_r).
             const C keep = C(1) - inv_vsT;
             const C s1 = n1 * keep, s2 = n2 * keep, s3 = n3 * keep;
-            const C s4 = fmad(P.wT0, T, -cg[0]) * (C(1) - P.gam_q);
+            const C s4 = fmad(P.wT0, T - nd.bt, -nd.r[0]) * (C(1) - P.gam_q);
             const C s5 = n5 * (C(1) - P.gam_pi), s6 = n6 * (C(1) - P.gam_pi);
             // Eqs. (23)-(24): Q = w (1.5 phi_s - 0.5 phi_s(t-1))
             C *phi_own = A.phi + own;
             const C qs = fmad(C(1.5), phis, C(-0.5) * *phi_own);
             const C Q0 = P.wT0 * qs, Q1 = P.wT1 * qs;
             // Eq. (40)-(41): g+ = N^-1 n* + Q = w T + N^-1 (n* - n_eq) + Q
-            const C wT = P.wT1 * T;
             const C c456 = (s4 + s5 + s6) * C(1.0 / 6.0);
             const C c3 = (s4 - C(2) * s5 + s6) * C(1.0 / 6.0), c5 = (s4 + s5 - C(2) * s6) * C(1.0 / 6.0);
-            gp[0] = (T - C(6) * wT) - s4 + Q0;
-            gp[1] = wT + (fmad(C(0.5), s1, c456) + Q1);
-            gp[2] = wT + (fmad(C(-0.5), s1, c456) + Q1);
-            gp[3] = wT + (fmad(C(0.5), s2, c3) + Q1);
-            gp[4] = wT + (fmad(C(-0.5), s2, c3) + Q1);
-            gp[5] = wT + (fmad(C(0.5), s3, c5) + Q1);
-            gp[6] = wT + (fmad(C(-0.5), s3, c5) + Q1);
+            gs[0] = Q0 - s4;
+            gs[1] = fmad(C(0.5), s1, c456) + Q1;
+            gs[2] = fmad(C(-0.5), s1, c456) + Q1;
+            gs[3] = fmad(C(0.5), s2, c3) + Q1;
+            gs[4] = fmad(C(-0.5), s2, c3) + Q1;
+            gs[5] = fmad(C(0.5), s3, c5) + Q1;
+            gs[6] = fmad(C(-0.5), s3, c5) + Q1;
             *phi_own = phis;
         }
 
@@ -569,82 +684,112 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<S, C> A) {
             Zo[2] = (unsigned)(z == nz - 1 ? 0 : z + 1) * PB;
         }
         const unsigned ownb = own * ES;
+        // Value to store for population a bound for the node whose ring slot
+        // is `slot`, offset (dx, dy): plain storage keeps f* (the rest part
+        // r0 closes the sum exactly: the rounded 1/3 + 6/18 + 12/36 is not 1);
+        // deviation storage encodes f* against the destination's reference.
+        const C r1 = rho * C(1.0 / 18.0), r2 = rho * C(1.0 / 36.0);
+        const C r0 = rho - fmad(C(6), r1, C(12) * r2);
+        auto fval = [&](int a, int slot, int dx, int dy) -> E {
+            if constexpr (DEV) {
+                const C bd = ST::rdec(ST::renc(s_rho[slot][li + dy * EX + dx]));
+                return ST::enc(fmad((C)w19(a), rho - bd, fs[a]));
+            } else {
+                return ST::enc(fs[a] + (a == 0 ? r0 : (a < 7 ? r1 : r2)));
+            }
+        };
 #pragma unroll
         for (int a = 0; a < 19; ++a) {
             const int ex = kE19X[a], ey = kE19Y[a], ez = kE19Z[a];
             const unsigned inrow = Yo[ey + 1] + Xo[ex + 1];
             if (WALLS) {
-                if (ez < 0 && z == 0) {  // Eq. (50): halfway bounce-back
-                    io.store(opposite(a), ownb, (S)fs[a]);
+                if (ez < 0 && z == 0) {  // Eq. (50): halfway bounce-back into the own node
+                    io.store(opposite(a), ownb, fval(a, s0, 0, 0));
                     continue;
                 }
                 if (ez > 0 && z == nz - 1) continue;  // leaves through the open top
                 if (ez < 0 && z == nz - 1)             // open top: unknown f copied from below
-                    io.store(a, Zc + inrow, (S)fs[a]);
+                    io.store(a, Zc + inrow, fval(a, s0, ex, ey));
             }
-            io.store(a, Zo[ez + 1] + inrow, (S)fs[a]);
+            io.store(a, Zo[ez + 1] + inrow, fval(a, sl[ez + 1], ex, ey));
         }
+        // D3Q7: g+ = w T_emit + gs; deviation storage subtracts w T_r of the
+        // destination.  A destination in the reservoir layer receives w T_shell.
+        const C wT = P.wT1 * T_emit, wT0 = T_emit - C(6) * wT;
+        const C wS = P.wT1 * P.T_shell, wS0 = P.T_shell - C(6) * wS;
+        auto gfull_minus_ref = [&](int a, int slot, int dx, int dy, bool to_shell) -> C {
+            if constexpr (DEV) {
+                const C bd = ST::rdec(ST::renc(s_tem[slot][li + dy * EX + dx]));
+                if (to_shell) return (a == 0 ? P.wT0 : P.wT1) * (P.T_shell - bd);
+                return fmad(a == 0 ? P.wT0 : P.wT1, T_emit - bd, gs[a]);
+            } else {
+                if (to_shell) return a == 0 ? wS0 : wS;
+                return (a == 0 ? wT0 : wT) + gs[a];
+            }
+        };
+        C own_tref = C(0);
+        if constexpr (DEV) own_tref = ST::rdec(ST::renc(T));
         if (P.thermal) {
 #pragma unroll
             for (int a = 0; a < 7; ++a) {
                 const int ex = kE7X[a], ey = kE7Y[a], ez = kE7Z[a];
                 if (WALLS) {
-                    if (ez < 0 && z == 0) {  // Eq. (51) at the wall
-                        io.store(G0 + opposite(a), ownb, (S)fmad(C(2) * P.wT1, T_bottom, -gp[a]));
-                        continue;
-                    }
-                    if (ez > 0 && z == nz - 1) {  // Eq. (51) with T_top
-                        io.store(G0 + opposite(a), ownb, (S)fmad(C(2) * P.wT1, (C)P.T_top, -gp[a]));
+                    // Eq. (51): g_opp(x_b) = -g+_a(x_b) + 2 w T_w, into the own node
+                    const bool bottom = ez < 0 && z == 0, top = ez > 0 && z == nz - 1;
+                    if (bottom || top) {
+                        const C Tw = bottom ? T_bottom : (C)P.T_top;
+                        const C v = DEV ? fmad(P.wT1, C(2) * Tw - T - own_tref, -gs[a])
+                                        : fmad(C(2) * P.wT1, Tw, -gfull_minus_ref(a, s0, 0, 0, false));
+                        io.store(G0 + opposite(a), ownb, ST::enc(v));
                         continue;
                     }
                 }
-                io.store(G0 + a, Zo[ez + 1] + Yo[ey + 1] + Xo[ex + 1], (S)gp[a]);
+                const bool to_shell = xs[ex + 1] || ys[ey + 1] || zs[ez + 1];
+                io.store(G0 + a, Zo[ez + 1] + Yo[ey + 1] + Xo[ex + 1],
+                         ST::enc(gfull_minus_ref(a, sl[ez + 1], ex, ey, to_shell)));
             }
         } else {
+            // temperature held fixed: g stays at the node (re-encoded against the new reference)
 #pragma unroll
-            for (int a = 0; a < 7; ++a) io.store(G0 + a, ownb, (S)cg[a]);
+            for (int a = 0; a < 7; ++a) {
+                const C v = DEV ? fmad(a == 0 ? P.wT0 : P.wT1, nd.bt - own_tref, nd.r[a]) : nd.r[a];
+                io.store(G0 + a, ownb, ST::enc(v));
+            }
+        }
+        if constexpr (DEV) {
+            io.store(RRHO, ownb, ST::renc(rho));
+            io.store(RT, ownb, ST::renc(T));
         }
         if (P.gravity) rho_sum += (double)rho;
     };
 
     // Software pipeline over the planes of the chunk.  At iteration z the
-    // populations of plane z (collision) and z+1 (moments) are in registers,
-    // and the loads of plane z+2 are issued right after the moments of z+1 so
-    // that their latency overlaps the barrier and the collision of plane z.
+    // states of plane z (collision) and z+1 (moments) are in registers, and
+    // the loads of plane z+2 are issued right after the moments of z+1 so that
+    // their latency overlaps the barrier and the collision of plane z.
     // (Issuing them earlier would put more memory operations between a load
     // and its use than the vmcnt counter can express, which forces a full
     // drain.)
-    C cf[19], cg[7], c_rho, c_T, c_psi;  // plane z
-    C nf[19], ng[7], nhf[19], nhg[7];    // plane z+1 (tile node, halo node)
-    C qf[19], qg[7], qhf[19], qhg[7];    // plane z+2
-    C n_rho, n_T, n_psi;
+    NodePops<C> cur, nxt, nxh, nq, nqh;  // plane z; plane z+1 (tile, halo); plane z+2
+    C c_rho, c_T, c_psi, n_rho, n_T, n_psi;
     {
-        C tf[19], tg[7], thf[19], thg[7], t0, t1, t2;
-        C hf0[19], hg0[7];
-        load_plane(z0 - 1, tf, tg, thf, thg);
-        load_plane(z0, cf, cg, hf0, hg0);
-        load_plane(z0 + 1, nf, ng, nhf, nhg);
-        plane_moments(0, tf, tg, thf, thg, t0, t1, t2);
-        plane_moments(1, cf, cg, hf0, hg0, c_rho, c_T, c_psi);
+        NodePops<C> t0, th0, h0;
+        C a0, a1, a2;
+        load_plane(z0 - 1, t0, th0);
+        load_plane(z0, cur, h0);
+        load_plane(z0 + 1, nxt, nxh);
+        plane_moments(0, t0, th0, a0, a1, a2);
+        plane_moments(1, cur, h0, c_rho, c_T, c_psi);
     }
     for (int z = z0; z < zend; ++z) {
         const int s = z - z0 + 1;
-        plane_moments((s + 1) & 3, nf, ng, nhf, nhg, n_rho, n_T, n_psi);
-        if (z + 2 <= zend) load_plane(z + 2, qf, qg, qhf, qhg);
+        plane_moments((s + 1) & 3, nxt, nxh, n_rho, n_T, n_psi);
+        if (z + 2 <= zend) load_plane(z + 2, nq, nqh);
         __syncthreads();
-        if (active) collide_stream(z, s, cf, cg, c_rho, c_T, c_psi);
-#pragma unroll
-        for (int a = 0; a < 19; ++a) {
-            cf[a] = nf[a];
-            nf[a] = qf[a];
-            nhf[a] = qhf[a];
-        }
-#pragma unroll
-        for (int a = 0; a < 7; ++a) {
-            cg[a] = ng[a];
-            ng[a] = qg[a];
-            nhg[a] = qhg[a];
-        }
+        if (active) collide_stream(z, s, cur, c_rho, c_T, c_psi);
+        cur = nxt;
+        nxt = nq;
+        nxh = nqh;
         c_rho = n_rho;
         c_T = n_T;
         c_psi = n_psi;
@@ -664,15 +809,28 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<S, C> A) {
 }
 
 // ---------------------------------------------------------------------------
-// Helper kernels (one thread per node; not on the per-step path).
+// Helper kernels (one thread per node; not on the per-step path).  They read
+// the state in FP64: a node's populations are w rho_r + e (e decoded), so
+// rho = rho_r + sum e and rho u = sum e_alpha e_alpha exactly.
 // ---------------------------------------------------------------------------
 
-// Initial populations from FP64 fields: f = M^-1 m_eq(rho, u), g = w T,
-// phi = 0; sets status bit 2 where rho <= 0, T <= 0 or psi^2 < 0.
-template <typename S, typename C>
-__global__ void __launch_bounds__(256) k_init(const double *__restrict__ stage, size_t nn, S *__restrict__ f,
-                                              S *__restrict__ g, C *__restrict__ phi, size_t st, Phys<double> P,
-                                              unsigned *__restrict__ status) {
+template <typename ST>
+struct NodeView {
+    const typename ST::T *pop;
+    size_t st;
+    __device__ double e(int a, size_t i) const { return ST::ddec(pop[a * st + i]); }
+    __device__ double ref(int k, size_t i) const {
+        if constexpr (ST::kDev) return (double)ST::rdec(pop[(26 + k) * st + i]);
+        else return 0.0;
+    }
+};
+
+// Initial state from FP64 fields: f = M^-1 m_eq(rho, u), g = w T, phi = 0;
+// sets status bit 2 where rho <= 0, T <= 0 or psi^2 < 0.
+template <typename ST>
+__global__ void __launch_bounds__(256) k_init(const double *__restrict__ stage, size_t nn,
+                                              typename ST::T *__restrict__ pop, typename ST::C *__restrict__ phi,
+                                              size_t st, Phys<double> P, unsigned *__restrict__ status) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nn) return;
     const double rho = stage[i], ux = stage[nn + i], uy = stage[2 * nn + i], uz = stage[3 * nn + i],
@@ -682,26 +840,34 @@ __global__ void __launch_bounds__(256) k_init(const double *__restrict__ stage, 
     double meq[19], fl[19];
     equilibrium19(rho, ux, uy, uz, meq);
     populations19(meq, fl);
+    double br = 0.0, bt = 0.0;
+    if constexpr (ST::kDev) {
+        br = (double)ST::rdec(ST::renc((float)rho));
+        bt = (double)ST::rdec(ST::renc((float)T));
+        pop[26 * st + i] = ST::renc((float)rho);
+        pop[27 * st + i] = ST::renc((float)T);
+    }
 #pragma unroll
-    for (int a = 0; a < 19; ++a) f[a * st + i] = (S)fl[a];
-    g[i] = (S)(P.wT0 * T);
+    for (int a = 0; a < 19; ++a) pop[a * st + i] = ST::denc(fl[a] - w19(a) * br);
+    pop[19 * st + i] = ST::denc(P.wT0 * (T - bt));
 #pragma unroll
-    for (int a = 1; a < 7; ++a) g[a * st + i] = (S)(P.wT1 * T);
-    phi[i] = C(0);
+    for (int a = 1; a < 7; ++a) pop[(19 + a) * st + i] = ST::denc(P.wT1 * (T - bt));
+    phi[i] = typename ST::C(0);
 }
 
 // Per-node rho, T (and psi) in FP64 into the staging planes 0, 4, 5.
-template <typename S>
-__global__ void __launch_bounds__(256) k_macro(const S *__restrict__ f, const S *__restrict__ g, size_t st, size_t nn,
+template <typename ST>
+__global__ void __launch_bounds__(256) k_macro(const typename ST::T *__restrict__ pop, size_t st, size_t nn,
                                                Phys<double> P, double *__restrict__ stage) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nn) return;
+    const NodeView<ST> v{pop, st};
     double fl[19], gl[7];
 #pragma unroll
-    for (int a = 0; a < 19; ++a) fl[a] = (double)f[a * st + i];
+    for (int a = 0; a < 19; ++a) fl[a] = v.e(a, i);
 #pragma unroll
-    for (int a = 0; a < 7; ++a) gl[a] = (double)g[a * st + i];
-    const double rho = sum19(fl), T = sum7(gl);
+    for (int a = 0; a < 7; ++a) gl[a] = v.e(19 + a, i);
+    const double rho = v.ref(0, i) + sum19(fl), T = v.ref(1, i) + sum7(gl);
     const double p2 = psi_squared(P, rho, T);
     stage[i] = rho;
     stage[4 * nn + i] = T;
@@ -709,10 +875,10 @@ __global__ void __launch_bounds__(256) k_macro(const S *__restrict__ f, const S 
 }
 
 // u of Eq. (10) with the total force, in FP64, into staging planes 1..3.
-template <typename S>
-__global__ void __launch_bounds__(256) k_velocity(const S *__restrict__ f, size_t st, int nx, int ny, int nz,
-                                                  int walls, Phys<double> P, const double *__restrict__ rho_ave,
-                                                  double *__restrict__ stage) {
+template <typename ST>
+__global__ void __launch_bounds__(256) k_velocity(const typename ST::T *__restrict__ pop, size_t st, int nx, int ny,
+                                                  int nz, int walls, Phys<double> P,
+                                                  const double *__restrict__ rho_ave, double *__restrict__ stage) {
     const size_t nn = (size_t)nx * ny * nz;
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nn) return;
@@ -726,16 +892,17 @@ __global__ void __launch_bounds__(256) k_velocity(const S *__restrict__ f, size_
         if (walls) zn = zn < 0 ? 0 : (zn > nz - 1 ? nz - 1 : zn);
         else zn = (zn + nz) % nz;
         const double w = (kE19X[a] * kE19X[a] + kE19Y[a] * kE19Y[a] + kE19Z[a] * kE19Z[a]) == 1 ? 1.0 / 6.0 : 1.0 / 12.0;
-        const double v = w * psi[((size_t)zn * ny + yn) * nx + xn];
-        Sp[0] += v * kE19X[a];
-        Sp[1] += v * kE19Y[a];
-        Sp[2] += v * kE19Z[a];
+        const double val = w * psi[((size_t)zn * ny + yn) * nx + xn];
+        Sp[0] += val * kE19X[a];
+        Sp[1] += val * kE19Y[a];
+        Sp[2] += val * kE19Z[a];
     }
     const double rho = stage[i];
+    const NodeView<ST> v{pop, st};
     double fl[19], m[19];
 #pragma unroll
-    for (int a = 0; a < 19; ++a) fl[a] = (double)f[a * st + i];
-    moments19(fl, m);
+    for (int a = 0; a < 19; ++a) fl[a] = v.e(a, i);
+    moments19(fl, m);  // m1..m3 of e equal those of f: sum e w_alpha = 0
     const double drho = P.gravity ? rho - *rho_ave : 0.0;
     const double F[3] = {P.negG * psi[i] * Sp[0] + drho * P.gx, P.negG * psi[i] * Sp[1] + drho * P.gy,
                          P.negG * psi[i] * Sp[2] + drho * P.gz};
@@ -743,20 +910,21 @@ __global__ void __launch_bounds__(256) k_velocity(const S *__restrict__ f, size_
 }
 
 // FP64 per-workgroup sums of rho and T of the current state.
-template <typename S>
-__global__ void __launch_bounds__(256) k_sum(const S *__restrict__ f, const S *__restrict__ g, size_t st, size_t nn,
+template <typename ST>
+__global__ void __launch_bounds__(256) k_sum(const typename ST::T *__restrict__ pop, size_t st, size_t nn,
                                              double *__restrict__ partials) {
     __shared__ double red[2][4];
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     double r = 0.0, t = 0.0;
     if (i < nn) {
+        const NodeView<ST> v{pop, st};
         double fl[19], gl[7];
 #pragma unroll
-        for (int a = 0; a < 19; ++a) fl[a] = (double)f[a * st + i];
+        for (int a = 0; a < 19; ++a) fl[a] = v.e(a, i);
 #pragma unroll
-        for (int a = 0; a < 7; ++a) gl[a] = (double)g[a * st + i];
-        r = sum19(fl);
-        t = sum7(gl);
+        for (int a = 0; a < 7; ++a) gl[a] = v.e(19 + a, i);
+        r = v.ref(0, i) + sum19(fl);
+        t = v.ref(1, i) + sum7(gl);
     }
     for (int o = 32; o > 0; o >>= 1) {
         r += __shfl_xor(r, o, 64);

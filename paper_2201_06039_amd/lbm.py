@@ -16,8 +16,10 @@ from . import build as _build
 OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
 BC_PERIODIC, BC_WALL_BOTTOM_OPEN_TOP = 0, 1
 KAPPA_CONST_LAMBDA, KAPPA_CONST_CHI = 0, 1
-STORE_F32, STORE_F64 = 0, 1
-_STORAGE_NAMES = {"f32": STORE_F32, "f64": STORE_F64}
+STORE_F32, STORE_F64, STORE_F16, STORE_BF16, STORE_F32_DEV = 0, 1, 2, 3, 4
+_STORAGE_NAMES = {"f32": STORE_F32, "f64": STORE_F64, "f16": STORE_F16, "bf16": STORE_BF16,
+                  "f32dev": STORE_F32_DEV}
+STORAGE_FORMATS = tuple(_STORAGE_NAMES)
 
 
 class LbmParams(ctypes.Structure):
@@ -32,6 +34,7 @@ class LbmParams(ctypes.Structure):
         ("T_wall_patch", ctypes.c_double), ("T_wall", ctypes.c_double),
         ("patch_radius", ctypes.c_double), ("T_top", ctypes.c_double),
         ("thermal", ctypes.c_int), ("storage", ctypes.c_int),
+        ("bc_T_shell", ctypes.c_int), ("T_shell", ctypes.c_double),
     ]
 
 
@@ -98,6 +101,8 @@ def make_params(params: dict, storage="f32") -> LbmParams:
     if "grav" in src and "g" not in src:
         src["g"] = src.pop("grav")
     src.setdefault("storage", _STORAGE_NAMES[storage] if isinstance(storage, str) else storage)
+    src.setdefault("bc_T_shell", 0)
+    src.setdefault("T_shell", 0.0)
     for n in names:
         if n not in src:
             raise KeyError(f"missing parameter {n!r}")

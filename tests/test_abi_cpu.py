@@ -53,6 +53,31 @@ def test_arena_bytes_and_validation(lib):
         assert lbm.arena_bytes(q) == 0, bad
 
 
+def test_arena_bytes_of_the_storage_formats(lib):
+    """Deviation formats hold 28 planes per copy (26 populations and the
+    rho_r, T_r references) of 2 bytes (f16, bf16) or 4 bytes (f32dev)."""
+    from paper_2201_06039_amd import lbm, workloads as W
+    p = W.load("evaporation_128")["params"]
+    n = 128 ** 3
+    rest = 4 * n + 6 * 8 * n  # FP32 phi history + FP64 staging
+    for fmt, planes, es in (("f16", 28, 2), ("bf16", 28, 2), ("f32dev", 28, 4), ("f32", 26, 4)):
+        b = lbm.arena_bytes(p, fmt)
+        assert 2 * planes * es * n + rest <= b < 2 * planes * es * n + rest + (1 << 22), fmt
+    assert set(lbm.STORAGE_FORMATS) == {"f32", "f64", "f16", "bf16", "f32dev"}
+
+
+def test_reservoir_boundary_validation(lib):
+    """The constant-temperature layer needs a periodic grid, a live
+    temperature lattice and a positive temperature."""
+    from paper_2201_06039_amd import lbm, workloads as W
+    p = dict(W.load("d2_law_48")["params"])
+    assert lbm.arena_bytes(p) > 0
+    for bad in (dict(bc_z=1), dict(thermal=0), dict(T_shell=0.0), dict(bc_T_shell=2)):
+        q = dict(p)
+        q.update(bad)
+        assert lbm.arena_bytes(q) == 0, bad
+
+
 def test_create_rejects_bad_arguments_before_any_device_call(lib):
     from paper_2201_06039_amd import lbm, workloads as W
     p = dict(W.load("static_droplet_32")["params"])

@@ -138,3 +138,22 @@ def test_constant_chi_and_minimal_grid_fp64():
     e = errors(run_gpu(w, 30, "f64"), run_oracle(w, 30))
     _say(f"  errors {e}")
     _check(e, FP64_TOL, keys=("rho", "T"))
+
+
+@pytest.mark.parametrize("launch", [None, (32, 8, 3)])
+def test_thermal_reservoir_boundary_fp64(launch):
+    """Constant-temperature boundary of the D^2 test: the outer layer of an
+    otherwise periodic 26 x 22 x 20 box is held at the vapour temperature
+    (ragged tiles and chunks put the layer at every tile and chunk edge)."""
+    w = workload("d2_law_48", nx=26, ny=22, nz=20, radius=6.0)
+    w["init"]["center"] = [12.4, 10.7, 9.3]
+    _say(f"reservoir boundary f64 launch={launch}")
+    got = run_gpu(w, 60, "f64", launch=launch)
+    e = errors(got, run_oracle(w, 60))
+    _say(f"  errors {e}")
+    _check(e, FP64_TOL)
+    T = got[4].reshape(20, 22, 26)
+    Ts = w["params"]["T_shell"]
+    for face in (T[0], T[-1], T[:, 0], T[:, -1], T[:, :, 0], T[:, :, -1]):
+        assert np.abs(face - Ts).max() <= 1e-14 * Ts
+

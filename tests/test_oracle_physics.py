@@ -257,6 +257,42 @@ def test_wall_conduction_profile(oracle_lib):
     np.testing.assert_allclose((T - Tt) / (Tw - Tt), (expect - Tt) / (Tw - Tt), atol=2e-3)
 
 
+def test_reservoir_layer_is_a_dirichlet_boundary(oracle_lib):
+    """Constant-temperature boundary of the D^2 test (Sec. IV A): the outer
+    layer of an L^3 box is held at T_s.  The layer's temperature stays T_s
+    exactly, and the fundamental conduction mode sin(pi x/L')sin(pi y/L')
+    sin(pi z/L') decays at 3 chi (pi/L')^2 with L' = L - 1 + 2 delta: the
+    effective Dirichlet point sits delta(chi) from the layer, within half a
+    spacing of it and the same for two box sizes (a diffusive boundary, not a
+    leak or a source)."""
+    for chi in (0.05, 0.2):
+        offsets = []
+        for L in (13, 25):
+            i = np.arange(L)
+            k = np.pi / (L - 1)
+            S = np.sin(k * i)
+            mode = S[:, None, None] * S[None, :, None] * S[None, None, :]
+            Ts = 1.0
+            ones = np.ones_like(mode)
+            s = oracle_lib.Sim(nx=L, ny=L, nz=L, a=0.0, b=0.0, R=0.0, kappa_mode=1, kappa=chi, bc_T_shell=1,
+                               T_shell=Ts)
+            s.init_fields(ones, 0 * ones, 0 * ones, 0 * ones, Ts + 1e-3 * mode)
+            dt = max(1, int(0.2 / (3 * chi * k * k)))
+            ts, amps = [], []
+            for j in range(16):
+                if j:
+                    s.step(dt)
+                T = s.rho_u_T()[4].reshape(L, L, L)
+                for face in (T[0], T[-1], T[:, 0], T[:, -1], T[:, :, 0], T[:, :, -1]):
+                    assert np.abs(face - Ts).max() <= 1e-15
+                ts.append(j * dt)
+                amps.append(((T - Ts) * mode).sum() / (mode * mode).sum())
+            rate = _decay_rate(ts[5:], amps[5:])
+            offsets.append((np.pi / np.sqrt(rate / (3 * chi)) - (L - 1)) / 2)
+        assert abs(offsets[0] - offsets[1]) < 0.05, (chi, offsets)
+        assert max(abs(o) for o in offsets) < 0.5, (chi, offsets)
+
+
 # --------------------------------------------------------------------------
 # printed values and thermodynamic consistency
 # --------------------------------------------------------------------------
