@@ -21,10 +21,11 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS (D3Q19+D3Q7 fused step) + % HBM peak, FP16-store vs FP32 at stated error"
 HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per lattice update: 19 + 7 populations (plus the two
-# reference values rho_r, T_r of the deviation formats) and the FP32 phi_s
-# history (FP64 for f64), each read once and written once.
-BYTES_PER_LUP = {"f32": 2 * 26 * 4 + 8, "f64": 2 * 26 * 8 + 16, "f16": 2 * 28 * 2 + 8, "bf16": 2 * 28 * 2 + 8,
-                 "f32dev": 2 * 28 * 4 + 8}
+# reference values rho_r, T_r of the deviation formats: FP16 for f16, FP32
+# for bf16 and f32dev) and the FP32 phi_s history (FP64 for f64), each read
+# once and written once.
+BYTES_PER_LUP = {"f32": 2 * 26 * 4 + 8, "f64": 2 * 26 * 8 + 16, "f16": 2 * (26 * 2 + 2 * 2) + 8,
+                 "bf16": 2 * (26 * 2 + 2 * 4) + 8, "f32dev": 2 * 28 * 4 + 8}
 KERNEL_SOURCES = ["paper_2201_06039_amd/csrc/lbm_kernels.hpp", "paper_2201_06039_amd/csrc/lbm_api.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_evaporation_128_traffic.json")
 

@@ -60,14 +60,15 @@ extern "C" {
  *   F16, BF16, F32_DEV: deviations from the rest equilibrium of a per-node
  *     reference, e = (f_alpha - w_alpha rho_r) s and r = (g_alpha - w_alpha T_r) s,
  *     with w_alpha the weights of Eq. (5) at u = 0 (1/3, 1/18, 1/36) and of
- *     the D3Q7 lattice (1 - d, d/6).  rho_r and T_r are the node's density and
- *     temperature one step earlier, rounded to the storage type and stored as
- *     two more planes; s = 1024 for F16 (keeps small deviations out of the
- *     subnormal range), 1 otherwise.  Arithmetic is FP32.  The moments are
- *     formed from e and the references directly, so the rest part (the O(rho)
- *     bulk of every population) is never rounded to the storage type: only
- *     deviations are.  Accuracy of these formats is a property of the
- *     workload (it is reported against the FP64 evolution, not assumed). */
+ *     the D3Q7 lattice (1 - d, d/6), in the storage type.  rho_r and T_r are
+ *     the node's density and temperature one step earlier, stored as two more
+ *     planes (FP16 for F16, FP32 for BF16 and F32_DEV); s = 1024 for F16
+ *     (keeps small deviations out of the subnormal range), 1 otherwise.
+ *     Arithmetic is FP32.  The moments are formed from e and the references
+ *     directly, so the rest part (the O(rho) bulk of every population) is
+ *     never rounded to the storage type: only deviations are.  Accuracy of
+ *     these formats is a property of the workload (it is measured against
+ *     the FP64 evolution, not assumed). */
 #define LBM_STORE_F32 0
 #define LBM_STORE_F64 1
 #define LBM_STORE_F16 2

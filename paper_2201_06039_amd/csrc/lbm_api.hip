@@ -23,7 +23,7 @@ struct TileShape {
 constexpr TileShape kTiles[] = {{64, 4}, {32, 8}, {64, 8}, {32, 16}, {128, 4}};
 
 struct Layout {
-    size_t nn, stride, es, cs, planes;
+    size_t nn, stride, es, rs, cs, planes;
     size_t off_pop[2], off_phi, off_stage, off_part, off_scal, total;
     size_t max_partials;
 };
@@ -40,8 +40,10 @@ size_t element_bytes(int s) {
     return 4;
 }
 
-// Planes per copy: 26 populations, plus rho_r and T_r for the deviation formats.
+// Planes per copy: 26 populations, plus rho_r and T_r for the deviation
+// formats (FP16 for F16, FP32 for BF16 and F32_DEV).
 size_t planes_of(int s) { return (s == LBM_STORE_F32 || s == LBM_STORE_F64) ? 26 : 28; }
+size_t reference_bytes(int s) { return s == LBM_STORE_F64 ? 8 : (s == LBM_STORE_F16 ? 2 : 4); }
 
 bool valid_params(const lbm_params *p) {
     if (!p) return false;
@@ -75,11 +77,20 @@ size_t max_workgroups(const lbm_params *p) {
     return best > sum_blocks ? best : sum_blocks;
 }
 
+size_t copy_bytes(const Layout &L) { return L.stride * (26 * L.es + (L.planes - 26) * L.rs); }
+
+// Byte offset of plane a (0..25 populations, 26..27 references) in a copy.
+size_t plane_offset(const Layout &L, size_t a) {
+    return a < 26 ? a * L.stride * L.es : 26 * L.stride * L.es + (a - 26) * L.stride * L.rs;
+}
+size_t plane_bytes(const Layout &L, size_t a) { return L.nn * (a < 26 ? L.es : L.rs); }
+
 Layout make_layout(const lbm_params *p) {
     Layout L;
     L.nn = (size_t)p->nx * p->ny * p->nz;
     L.es = element_bytes(p->storage);
     L.cs = p->storage == LBM_STORE_F64 ? 8 : 4;
+    L.rs = reference_bytes(p->storage);
     L.planes = planes_of(p->storage);
     L.stride = align_up(L.nn, 128);
     // Each ping-pong copy holds its planes contiguously, `stride` elements
@@ -87,7 +98,7 @@ Layout make_layout(const lbm_params *p) {
     size_t off = 0;
     for (int k = 0; k < 2; ++k) {
         L.off_pop[k] = off;
-        off = align_up(off + L.planes * L.stride * L.es, kAlign);
+        off = align_up(off + copy_bytes(L), kAlign);
     }
     L.off_phi = off;
     off = align_up(off + L.stride * L.cs, kAlign);
@@ -230,7 +241,11 @@ int workgroups_for(const lbm_handle *h, int tx, int ty, int cz) {
 
 // The buffer-resource path addresses each half of a copy's planes (split at
 // plane 14) with 32-bit offsets.
-bool buffer_path(const Layout &L) { return (size_t)lbm::kSplitPlane * L.stride * L.es <= 0xFFFFFFFFull; }
+bool buffer_path(const Layout &L) {
+    const size_t lo = (size_t)lbm::kSplitPlane * L.stride * L.es;
+    const size_t hi = copy_bytes(L) - lo;
+    return lo <= 0xFFFFFFFFull && hi <= 0xFFFFFFFFull;
+}
 
 template <typename ST, int TX, int TY, bool WALLS>
 int launch_step_t(lbm_handle *h, const lbm::StepArgs<ST> &A, int nb) {
@@ -455,7 +470,9 @@ int lbm_reduce(lbm_handle *h, double *mass, double *energy) {
 size_t lbm_state_bytes(const lbm_handle *h) {
     if (!h) return 0;
     const size_t nn = h->L.nn;
-    return sizeof(StateHeader) + h->L.planes * nn * h->L.es + nn * h->L.cs + sizeof(double);
+    size_t planes = 0;
+    for (size_t a = 0; a < h->L.planes; ++a) planes += plane_bytes(h->L, a);
+    return sizeof(StateHeader) + planes + nn * h->L.cs + sizeof(double);
 }
 
 int lbm_get_state(lbm_handle *h, void *host_buf, size_t bytes) {
@@ -476,11 +493,13 @@ int lbm_get_state(lbm_handle *h, void *host_buf, size_t bytes) {
     char *out = (char *)host_buf;
     memcpy(out, &hd, sizeof(hd));
     out += sizeof(hd);
-    const size_t plane = h->L.nn * h->L.es;
-    for (size_t a = 0; a < h->L.planes; ++a, out += plane)
-        if (hipMemcpyAsync(out, (char *)h->pop(h->cur) + a * h->L.stride * h->L.es, plane, hipMemcpyDeviceToHost,
+    for (size_t a = 0; a < h->L.planes; ++a) {
+        const size_t bytes = plane_bytes(h->L, a);
+        if (hipMemcpyAsync(out, (char *)h->pop(h->cur) + plane_offset(h->L, a), bytes, hipMemcpyDeviceToHost,
                            h->stream) != hipSuccess)
             return LBM_EHIP;
+        out += bytes;
+    }
     if (hipMemcpyAsync(out, h->phi(), h->L.nn * h->L.cs, hipMemcpyDeviceToHost, h->stream) != hipSuccess)
         return LBM_EHIP;
     out += h->L.nn * h->L.cs;
@@ -505,12 +524,14 @@ int lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes) {
         hd.nn != h->L.nn || hd.es != h->L.es || hd.cs != h->L.cs)
         return LBM_EINVAL;
     const char *in = (const char *)host_buf + sizeof(hd);
-    const size_t plane = h->L.nn * h->L.es;
     h->cur = 0;
-    for (size_t a = 0; a < h->L.planes; ++a, in += plane)
-        if (hipMemcpyAsync((char *)h->pop(0) + a * h->L.stride * h->L.es, in, plane, hipMemcpyHostToDevice,
-                           h->stream) != hipSuccess)
+    for (size_t a = 0; a < h->L.planes; ++a) {
+        const size_t bytes = plane_bytes(h->L, a);
+        if (hipMemcpyAsync((char *)h->pop(0) + plane_offset(h->L, a), in, bytes, hipMemcpyHostToDevice, h->stream) !=
+            hipSuccess)
             return LBM_EHIP;
+        in += bytes;
+    }
     if (hipMemcpyAsync(h->phi(), in, h->L.nn * h->L.cs, hipMemcpyHostToDevice, h->stream) != hipSuccess)
         return LBM_EHIP;
     in += h->L.nn * h->L.cs;

@@ -232,15 +232,28 @@ __device__ __forceinline__ double fmad(double a, double b, double c) { return __
 // Storage formats of the populations.
 // ---------------------------------------------------------------------------
 
-// Each format: T = stored element, C = compute type, kDev = deviation
-// encoding with references, kScale = factor applied to stored deviations
-// (keeps FP16 deviations above the subnormal range).  dec/enc map stored
-// deviations (or raw populations) to C and back; rdec/renc do the same for
-// the unscaled references.
+// Each format: T = stored population element, R = stored reference element,
+// C = compute type, kDev = deviation encoding against per-node references,
+// kScale = factor K of the stored deviations (keeps FP16 deviations above the
+// subnormal range).  dec/enc are plain conversions between T and C: the step
+// kernel works on K-scaled deviations throughout.  rdec/renc convert the
+// (unscaled) references; ddec/denc give the unscaled value in FP64 for the
+// helper kernels.
+//
+// References: FP16 stores them as FP16.  rho - rho_r (up to rho 2^-12) then
+// enters every deviation as a node-to-node irregular offset w (rho - rho_r),
+// which keeps the FP16 rounding errors of neighbouring nodes uncorrelated.
+// With exact (FP32) references the deviations of a smooth region are smooth
+// too, their rounding errors line up, and the bias shows as a systematic
+// drift (measured: a 5x larger error of the D^2 slope of an evaporating
+// droplet).  BF16 keeps FP32 references: its 8-bit rounding of the reference
+// would put offsets of up to w rho 2^-9 into every deviation.
 struct StoreF32 {
     using T = float;
+    using R = float;
     using C = float;
     static constexpr bool kDev = false;
+    static constexpr float kScale = 1.0f;
     __device__ static C dec(T v) { return v; }
     __device__ static T enc(C v) { return v; }
     __device__ static C rdec(T v) { return v; }
@@ -250,8 +263,10 @@ struct StoreF32 {
 };
 struct StoreF64 {
     using T = double;
+    using R = double;
     using C = double;
     static constexpr bool kDev = false;
+    static constexpr double kScale = 1.0;
     __device__ static C dec(T v) { return v; }
     __device__ static T enc(C v) { return v; }
     __device__ static C rdec(T v) { return v; }
@@ -261,8 +276,10 @@ struct StoreF64 {
 };
 struct StoreF32Dev {
     using T = float;
+    using R = float;
     using C = float;
     static constexpr bool kDev = true;
+    static constexpr float kScale = 1.0f;
     __device__ static C dec(T v) { return v; }
     __device__ static T enc(C v) { return v; }
     __device__ static C rdec(T v) { return v; }
@@ -272,30 +289,30 @@ struct StoreF32Dev {
 };
 struct StoreF16 {
     using T = _Float16;
+    using R = _Float16;
     using C = float;
     static constexpr bool kDev = true;
-    static constexpr float kScale = 1024.0f, kInv = 1.0f / 1024.0f;
-    __device__ static C dec(T v) { return (float)v * kInv; }
-    __device__ static T enc(C v) { return (T)(v * kScale); }
-    __device__ static C rdec(T v) { return (float)v; }
-    __device__ static T renc(C v) { return (T)v; }
+    static constexpr float kScale = 1024.0f;
+    __device__ static C dec(T v) { return (float)v; }
+    __device__ static T enc(C v) { return (T)v; }
+    __device__ static C rdec(R v) { return (float)v; }
+    __device__ static R renc(C v) { return (R)v; }
     __device__ static double ddec(T v) { return (double)(float)v * (1.0 / 1024.0); }
     __device__ static T denc(double v) { return (T)(float)(v * 1024.0); }
 };
 struct StoreBF16 {  // conversions round to nearest even (v_cvt_pk_bf16_f32 on gfx950)
     using T = __bf16;
+    using R = float;
     using C = float;
     static constexpr bool kDev = true;
+    static constexpr float kScale = 1.0f;
     __device__ static C dec(T v) { return (float)v; }
     __device__ static T enc(C v) { return (T)v; }
-    __device__ static C rdec(T v) { return (float)v; }
-    __device__ static T renc(C v) { return (T)v; }
+    __device__ static C rdec(R v) { return v; }
+    __device__ static R renc(C v) { return v; }
     __device__ static double ddec(T v) { return (double)(float)v; }
     __device__ static T denc(double v) { return (T)(float)v; }
 };
-
-template <typename ST>
-constexpr int planes_of() { return ST::kDev ? 28 : 26; }
 
 // Loads/stores of a 2-, 4- or 8-byte element through a buffer resource.
 template <typename T>
@@ -318,23 +335,28 @@ __device__ __forceinline__ void buf_st(T x, __amdgpu_buffer_rsrc_t r, unsigned v
 
 constexpr int kBufferFlags = 0x00020000;  // raw dword buffer; the record count is left at its maximum and
                                           // every offset is kept inside the planes by construction
-constexpr int kSplitPlane = 14;           // planes [0,14) and [14,28) sit behind two resources
+constexpr int kSplitPlane = 14;           // population planes [0,14) and [14,26) + references: two resources
+constexpr int kPopPlanes = 26;
 
-// Access to the population planes of the two ping-pong copies.
-//  BUF = true: two buffer resources per copy (planes below and from plane 14);
-//  a plane's offset is a scalar and the node's byte offset one 32-bit vector
-//  offset shared by all planes, so loads cost no vector address arithmetic.
-//  Needs 14 planes to span less than 4 GiB.
+// Access to the planes of the two ping-pong copies.  A copy holds 26
+// population planes of T, `stride` elements apart, then (deviation formats)
+// the rho_r and T_r planes of R, `stride` elements apart.
+//  BUF = true: two buffer resources per copy (planes below plane 14, and the
+//  rest); a plane's offset is a scalar and the node's byte offset one 32-bit
+//  vector offset shared by all planes, so loads cost no vector address
+//  arithmetic.  Needs each half to span less than 4 GiB.
 //  BUF = false: plain global pointers (any size).
-template <typename T, bool BUF>
+template <typename T, typename R, bool BUF>
 struct PopIO;
 
-template <typename T>
-struct PopIO<T, true> {
+template <typename T, typename R>
+struct PopIO<T, R, true> {
     __amdgpu_buffer_rsrc_t in_lo, in_hi, out_lo, out_hi;
-    unsigned sb;  // plane stride in bytes
+    unsigned sb;   // population plane stride in bytes
+    unsigned rsb;  // reference plane stride in bytes
     __device__ PopIO(const T *pin, T *pout, size_t stride) {
         sb = (unsigned)(stride * sizeof(T));
+        rsb = (unsigned)(stride * sizeof(R));
         in_lo = __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(pin), 0, -1, kBufferFlags);
         in_hi = __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(pin) + kSplitPlane * stride, 0, -1, kBufferFlags);
         out_lo = __builtin_amdgcn_make_buffer_rsrc(pout, 0, -1, kBufferFlags);
@@ -348,10 +370,17 @@ struct PopIO<T, true> {
         if (a < kSplitPlane) buf_st<T>(v, out_lo, boff, (unsigned)a * sb);
         else buf_st<T>(v, out_hi, boff, (unsigned)(a - kSplitPlane) * sb);
     }
+    // reference plane k (0: rho_r, 1: T_r); rboff = node index * sizeof(R)
+    __device__ R load_ref(int k, unsigned rboff) const {
+        return buf_ld<R>(in_hi, rboff, (unsigned)(kPopPlanes - kSplitPlane) * sb + (unsigned)k * rsb);
+    }
+    __device__ void store_ref(int k, unsigned rboff, R v) const {
+        buf_st<R>(v, out_hi, rboff, (unsigned)(kPopPlanes - kSplitPlane) * sb + (unsigned)k * rsb);
+    }
 };
 
-template <typename T>
-struct PopIO<T, false> {
+template <typename T, typename R>
+struct PopIO<T, R, false> {
     const T *in;
     T *out;
     size_t st;
@@ -361,6 +390,14 @@ struct PopIO<T, false> {
     }
     __device__ void store(int a, unsigned boff, T v) const {
         *reinterpret_cast<T *>(reinterpret_cast<char *>(out + a * st) + boff) = v;
+    }
+    __device__ R load_ref(int k, unsigned rboff) const {
+        const R *base = reinterpret_cast<const R *>(in + kPopPlanes * st) + k * st;
+        return *reinterpret_cast<const R *>(reinterpret_cast<const char *>(base) + rboff);
+    }
+    __device__ void store_ref(int k, unsigned rboff, R v) const {
+        R *base = reinterpret_cast<R *>(out + kPopPlanes * st) + k * st;
+        *reinterpret_cast<R *>(reinterpret_cast<char *>(base) + rboff) = v;
     }
 };
 
@@ -386,8 +423,9 @@ __device__ __forceinline__ int xcd_logical_block(int b, int nb) {
     return xcd * q + (xcd < r ? xcd : r) + (b >> 3);
 }
 
-// One node's loaded state: e = stored populations decoded to C (deviations
-// for the deviation formats), br/bt = references (0 for plain storage).
+// One node's loaded state in the compute type: e, r = stored f and g values
+// (K-scaled deviations for the deviation formats), br/bt = references
+// (0 for plain storage).
 template <typename C>
 struct NodePops {
     C e[19], r[7], br, bt;
@@ -398,19 +436,26 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
     using E = typename ST::T;  // stored element
     using C = typename ST::C;
     constexpr bool DEV = ST::kDev;
+    constexpr C K = ST::kScale, IK = C(1) / ST::kScale;
     constexpr int NT = TX * TY, EX = TX + 2, EY = TY + 2, NE = EX * EY, NH = NE - NT;
     static_assert(NH <= NT, "halo must not exceed the tile");
     constexpr unsigned ES = sizeof(E);
-    constexpr int G0 = 19, RRHO = 26, RT = 27;  // first D3Q7 plane, reference planes
+    constexpr int G0 = 19;  // first D3Q7 plane
+    constexpr unsigned RSZ = sizeof(typename ST::R);
+    // References in the compute type need no LDS copy of rho of their own.
+    constexpr bool OWN_RREF = DEV && sizeof(typename ST::R) != sizeof(C);
+    constexpr int RS = OWN_RREF ? 4 : 1, RN = OWN_RREF ? NE : 1;
+    constexpr int TS = DEV ? 4 : 1, TN = DEV ? NE : 1;
     __shared__ C s_psi[4][NE];
     __shared__ C s_rho[4][NE];
-    __shared__ C s_tem[DEV ? 4 : 1][DEV ? NE : 1];
+    __shared__ C s_rref[RS][RN];  // rho and T as stored in the reference planes:
+    __shared__ C s_tref[TS][TN];  // the references every node writes for itself
     __shared__ double s_red[NT / 64];
 
     const Phys<C> &P = A.P;
     const int nx = A.nx, ny = A.ny, nz = A.nz;
     const unsigned plane = (unsigned)nx * (unsigned)ny;
-    const PopIO<E, BUF> io(A.pop_in, A.pop_out, A.stride);
+    const PopIO<E, typename ST::R, BUF> io(A.pop_in, A.pop_out, A.stride);
 
     const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
     const int itx = logical % A.ntx;
@@ -451,14 +496,15 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
         return zz < 0 ? zz + nz : zz;
     };
 
-    auto load_node = [&](unsigned b, NodePops<C> &n) {
+    auto load_node = [&](unsigned node, NodePops<C> &n) {
+        const unsigned b = node * ES;
 #pragma unroll
         for (int a = 0; a < 19; ++a) n.e[a] = ST::dec(io.load(a, b));
 #pragma unroll
         for (int a = 0; a < 7; ++a) n.r[a] = ST::dec(io.load(G0 + a, b));
         if constexpr (DEV) {
-            n.br = ST::rdec(io.load(RRHO, b));
-            n.bt = ST::rdec(io.load(RT, b));
+            n.br = ST::rdec(io.load_ref(0, node * RSZ));
+            n.bt = ST::rdec(io.load_ref(1, node * RSZ));
         } else {
             n.br = C(0);
             n.bt = C(0);
@@ -467,13 +513,23 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
     // State of plane zp for this thread's tile node and its halo node.
     auto load_plane = [&](int zp, NodePops<C> &k, NodePops<C> &h) {
         const unsigned zoff = (unsigned)zmap(zp) * plane;
-        load_node((zoff + irow) * ES, k);
-        if (has_halo) load_node((zoff + hrow) * ES, h);
+        load_node(zoff + irow, k);
+        if (has_halo) load_node(zoff + hrow, h);
     };
 
-    // rho, T, psi of a loaded plane (tile node and halo node) -> LDS slot.
+    // rho = rho_r + sum e / K and T = T_r + sum r / K of a loaded node.
+    auto node_rho = [&](const NodePops<C> &n) -> C {
+        if constexpr (DEV) return fmad(sum19(n.e), IK, n.br);
+        else return sum19(n.e);
+    };
+    auto node_T = [&](const NodePops<C> &n) -> C {
+        if constexpr (DEV) return fmad(sum7(n.r), IK, n.bt);
+        else return sum7(n.r);
+    };
+    // rho, T, psi (and the rounded references) of a loaded plane, tile node
+    // and halo node, into LDS slot `slot`.
     auto plane_moments = [&](int slot, const NodePops<C> &k, const NodePops<C> &h, C &krho, C &kT, C &kpsi) {
-        const C rho = k.br + sum19(k.e), T = k.bt + sum7(k.r);
+        const C rho = node_rho(k), T = node_T(k);
         const C p2 = psi_squared(P, rho, T);
         // Unstable node (rho <= 0, psi^2 < 0 or NaN): one flag update per wave.
         const bool bad = active && (!(rho > C(0)) || !(p2 >= C(0)));
@@ -482,16 +538,18 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
         const C psi = Num<C>::sqrt(p2 > C(0) ? p2 : C(0));
         s_psi[slot][li] = psi;
         s_rho[slot][li] = rho;
-        if constexpr (DEV) s_tem[slot][li] = T;
+        if constexpr (OWN_RREF) s_rref[slot][li] = ST::rdec(ST::renc(rho));
+        if constexpr (DEV) s_tref[slot][li] = ST::rdec(ST::renc(T));
         krho = rho;
         kT = T;
         kpsi = psi;
         if (has_halo) {
-            const C hr = h.br + sum19(h.e), hT = h.bt + sum7(h.r);
+            const C hr = node_rho(h), hT = node_T(h);
             const C hp2 = psi_squared(P, hr, hT);
             s_psi[slot][hli] = Num<C>::sqrt(hp2 > C(0) ? hp2 : C(0));
             s_rho[slot][hli] = hr;
-            if constexpr (DEV) s_tem[slot][hli] = hT;
+            if constexpr (OWN_RREF) s_rref[slot][hli] = ST::rdec(ST::renc(hr));
+            if constexpr (DEV) s_tref[slot][hli] = ST::rdec(ST::renc(hT));
         }
     };
 
@@ -509,7 +567,9 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
     double rho_sum = 0.0;
 
     // Collision and streaming of the tile node at plane z (slot s of the ring
-    // holds plane z; s-1 and s+1 its neighbours).
+    // holds plane z; s-1 and s+1 its neighbours).  All population-space
+    // quantities (moments, equilibria, sources, post-collision values) are
+    // carried K-scaled, so the stored values convert without a multiply.
     auto collide_stream = [&](int z, int s, const NodePops<C> &nd, C rho, C T, C psi) {
         const int sm = (s + 3) & 3, s0 = s & 3, sp = (s + 1) & 3;
         const int sl[3] = {sm, s0, sp};
@@ -539,23 +599,25 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
             Fy = fmad(drho, P.gy, Fy);
             Fz = fmad(drho, P.gz, Fz);
         }
+        // K-scaled force and density (K = 1 for the plain formats).
+        const C FxK = K * Fx, FyK = K * Fy, FzK = K * Fz, rhoK = K * rho, inv_rhoK = IK * inv_rho;
         // Moments as deviations from the rest equilibrium w rho.  The rest
         // part is conserved by the collision (Lambda_0 = 1, S_0 = 0, and
         // m_eq(rho, 0) relaxes onto itself), so it is added back to f* at the
         // end instead of being carried through O(rho) sums.  With e the
-        // stored values (f - w rho_r), rho - rho_r = sum e plays the role of
-        // rho in the rest-part subtraction.
+        // stored values K (f - w rho_r), K (rho - rho_r) = sum e plays the
+        // role of rho in the rest-part subtraction.
         C m[19];
-        moments19<C, true>(nd.e, m, rho - nd.br);
+        moments19<C, true>(nd.e, m, K * (rho - nd.br));
         // Eq. (10)
-        const C ux = fmad(C(0.5), Fx, m[1]) * inv_rho;
-        const C uy = fmad(C(0.5), Fy, m[2]) * inv_rho;
-        const C uz = fmad(C(0.5), Fz, m[3]) * inv_rho;
+        const C ux = fmad(C(0.5), FxK, m[1]) * inv_rhoK;
+        const C uy = fmad(C(0.5), FyK, m[2]) * inv_rhoK;
+        const C uz = fmad(C(0.5), FzK, m[3]) * inv_rhoK;
         // Eq. (5) for m5..m15, and the deviations from m_eq(rho, 0) of m4
         // and m16..m18 (m4 - rho, m16..18 - rho/9).
         constexpr C cs2 = C(1.0 / 3.0);
-        const C rux = rho * ux, ruy = rho * uy, ruz = rho * uz;
-        const C r3 = rho * cs2;
+        const C rux = rhoK * ux, ruy = rhoK * uy, ruz = rhoK * uz;
+        const C r3 = rhoK * cs2;
         const C rxx = rux * ux, ryy = ruy * uy, rzz = ruz * uz;  // rho u_i^2
         const C r6 = C(0.5) * cs2 * (rxx + ryy + rzz);           // rho |u|^2 / 6
         C meq[19];
@@ -575,39 +637,39 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
         meq[17] = fmad(cs2, rxx + rzz, -r6);
         meq[18] = fmad(cs2, ryy + rzz, -r6);
         // Eq. (9)
-        const C xFx = ux * Fx, yFy = uy * Fy, zFz = uz * Fz;
+        const C xFx = ux * FxK, yFy = uy * FyK, zFz = uz * FzK;
         const C Fu = xFx + yFy + zFz;
         const C fm2 = fmad(fmx, fmx, fmad(fmy, fmy, fmz * fmz));
-        const C S4 = fmad(P.sig6 * fm2, Num<C>::rcp(psi * psi), C(2) * Fu);
+        const C S4 = fmad(P.sig6 * K * fm2, Num<C>::rcp(psi * psi), C(2) * Fu);
         // Eq. (3): m* = m + Lambda (m_eq - m) + (I - Lambda/2) S
         C ms[19];
         ms[0] = C(0);
-        ms[1] = m[1] + Fx;
-        ms[2] = m[2] + Fy;
-        ms[3] = m[3] + Fz;
+        ms[1] = m[1] + FxK;
+        ms[2] = m[2] + FyK;
+        ms[3] = m[3] + FzK;
         ms[4] = fmad(P.lam_e, meq[4] - m[4], fmad(C(1) - C(0.5) * P.lam_e, S4, m[4]));
         const C hv = C(1) - C(0.5) * P.lam_v;
         ms[5] = fmad(P.lam_v, meq[5] - m[5], fmad(hv * C(2), C(2) * xFx - yFy - zFz, m[5]));
         ms[6] = fmad(P.lam_v, meq[6] - m[6], fmad(hv * C(2), yFy - zFz, m[6]));
-        ms[7] = fmad(P.lam_v, meq[7] - m[7], fmad(hv, fmad(Fx, uy, Fy * ux), m[7]));
-        ms[8] = fmad(P.lam_v, meq[8] - m[8], fmad(hv, fmad(Fx, uz, Fz * ux), m[8]));
-        ms[9] = fmad(P.lam_v, meq[9] - m[9], fmad(hv, fmad(Fy, uz, Fz * uy), m[9]));
+        ms[7] = fmad(P.lam_v, meq[7] - m[7], fmad(hv, fmad(FxK, uy, FyK * ux), m[7]));
+        ms[8] = fmad(P.lam_v, meq[8] - m[8], fmad(hv, fmad(FxK, uz, FzK * ux), m[8]));
+        ms[9] = fmad(P.lam_v, meq[9] - m[9], fmad(hv, fmad(FyK, uz, FzK * uy), m[9]));
         const C hq = (C(1) - C(0.5) * P.lam_q) * cs2;
-        ms[10] = fmad(P.lam_q, meq[10] - m[10], fmad(hq, Fy, m[10]));
-        ms[11] = fmad(P.lam_q, meq[11] - m[11], fmad(hq, Fx, m[11]));
-        ms[12] = fmad(P.lam_q, meq[12] - m[12], fmad(hq, Fz, m[12]));
-        ms[13] = fmad(P.lam_q, meq[13] - m[13], fmad(hq, Fx, m[13]));
-        ms[14] = fmad(P.lam_q, meq[14] - m[14], fmad(hq, Fz, m[14]));
-        ms[15] = fmad(P.lam_q, meq[15] - m[15], fmad(hq, Fy, m[15]));
+        ms[10] = fmad(P.lam_q, meq[10] - m[10], fmad(hq, FyK, m[10]));
+        ms[11] = fmad(P.lam_q, meq[11] - m[11], fmad(hq, FxK, m[11]));
+        ms[12] = fmad(P.lam_q, meq[12] - m[12], fmad(hq, FzK, m[12]));
+        ms[13] = fmad(P.lam_q, meq[13] - m[13], fmad(hq, FxK, m[13]));
+        ms[14] = fmad(P.lam_q, meq[14] - m[14], fmad(hq, FzK, m[14]));
+        ms[15] = fmad(P.lam_q, meq[15] - m[15], fmad(hq, FyK, m[15]));
         const C hp = (C(1) - C(0.5) * P.lam_pi) * C(2) * cs2;
         ms[16] = fmad(P.lam_pi, meq[16] - m[16], fmad(hp, xFx + yFy, m[16]));
         ms[17] = fmad(P.lam_pi, meq[17] - m[17], fmad(hp, xFx + zFz, m[17]));
         ms[18] = fmad(P.lam_pi, meq[18] - m[18], fmad(hp, yFy + zFz, m[18]));
-        C fs[19];  // f* - w rho
+        C fs[19];  // K (f* - w rho)
         populations19(ms, fs);
 
         // ---- D3Q7 thermal lattice ----
-        C gs[7];  // g+ - w T_emit
+        C gs[7];  // K (g+ - w T_emit)
         const unsigned own = (unsigned)z * plane + irow;
         // Constant-temperature boundary (Sec. IV A): the outer layer of nodes
         // is a reservoir at T_shell.  It emits w T_shell without collision,
@@ -633,15 +695,15 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
             for (int a = 0; a < 7; ++a) gs[a] = C(0);
         } else if (P.thermal) {
             // Eq. (48): local velocity divergence (pre-collision m_4).
-            const C divu = fmad(P.divu_b, S4, -fmad(P.divu_a, m[4] - meq[4], C(2) * Fu)) * (C(1.5) * inv_rho);
+            const C divu = fmad(P.divu_b, S4, -fmad(P.divu_a, m[4] - meq[4], C(2) * Fu)) * (C(1.5) * inv_rhoK);
             // Eq. (38): n = N g (the reference part w T_r cancels from n1..n3, n5, n6)
             const C n1 = nd.r[1] - nd.r[2], n2 = nd.r[3] - nd.r[4], n3 = nd.r[5] - nd.r[6];
             const C a12 = nd.r[1] + nd.r[2], a34 = nd.r[3] + nd.r[4], a56 = nd.r[5] + nd.r[6];
             const C n5 = a12 - a34, n6 = a12 - a56;
             const C chi = P.kappa_mode ? P.kappa : P.kappa * inv_rho * P.inv_cV;
             const C inv_vsT = Num<C>::rcp(fmad(chi, P.inv_csT2, C(0.5)));
-            // Eq. (45): local temperature gradient.
-            const C kgr = -inv_vsT * P.inv_csT2;
+            // Eq. (45): local temperature gradient (n is K-scaled).
+            const C kgr = -inv_vsT * (P.inv_csT2 * IK);
             const C dTx = kgr * n1, dTy = kgr * n2, dTz = kgr * n3;
             // Eq. (18) with (dp/dT)_rho = rho R/(1 - b rho), constant c_V.
             const C cr = chi * inv_rho;
@@ -651,12 +713,12 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
             // n4 - d T = (1 - d) T - g0 = w0 (T - T_r) - (g0 - w0 T_r).
             const C keep = C(1) - inv_vsT;
             const C s1 = n1 * keep, s2 = n2 * keep, s3 = n3 * keep;
-            const C s4 = fmad(P.wT0, T - nd.bt, -nd.r[0]) * (C(1) - P.gam_q);
+            const C s4 = fmad(K * P.wT0, T - nd.bt, -nd.r[0]) * (C(1) - P.gam_q);
             const C s5 = n5 * (C(1) - P.gam_pi), s6 = n6 * (C(1) - P.gam_pi);
             // Eqs. (23)-(24): Q = w (1.5 phi_s - 0.5 phi_s(t-1))
             C *phi_own = A.phi + own;
             const C qs = fmad(C(1.5), phis, C(-0.5) * *phi_own);
-            const C Q0 = P.wT0 * qs, Q1 = P.wT1 * qs;
+            const C Q0 = (K * P.wT0) * qs, Q1 = (K * P.wT1) * qs;
             // Eq. (40)-(41): g+ = N^-1 n* + Q = w T + N^-1 (n* - n_eq) + Q
             const C c456 = (s4 + s5 + s6) * C(1.0 / 6.0);
             const C c3 = (s4 - C(2) * s5 + s6) * C(1.0 / 6.0), c5 = (s4 + s5 - C(2) * s6) * C(1.0 / 6.0);
@@ -684,18 +746,35 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
             Zo[2] = (unsigned)(z == nz - 1 ? 0 : z + 1) * PB;
         }
         const unsigned ownb = own * ES;
-        // Value to store for population a bound for the node whose ring slot
-        // is `slot`, offset (dx, dy): plain storage keeps f* (the rest part
-        // r0 closes the sum exactly: the rounded 1/3 + 6/18 + 12/36 is not 1);
-        // deviation storage encodes f* against the destination's reference.
+        // Values stored for the D3Q19 population a bound for the node in ring
+        // slot `slot` at offset (dx, dy).  Plain storage keeps f* (the rest
+        // part r0 closes the sum exactly: the rounded 1/3 + 6/18 + 12/36 is
+        // not 1).  Deviation storage encodes K (f* - w rho_r(dest)) as
+        // A_a + K w (rho_r(own) - rho_r(dest)) with A_a = K (f* - w rho_r(own)),
+        // so that A_a carries no O(rho) part.
+        auto rref = [&](int slot, int idx) -> C {
+            if constexpr (OWN_RREF) return s_rref[slot][idx];
+            else return s_rho[slot][idx];
+        };
+        C own_rref = C(0), own_tref = C(0);
+        if constexpr (DEV) {
+            own_rref = rref(s0, li);
+            own_tref = s_tref[s0][li];
+        }
         const C r1 = rho * C(1.0 / 18.0), r2 = rho * C(1.0 / 36.0);
         const C r0 = rho - fmad(C(6), r1, C(12) * r2);
+        C fa[19];
+#pragma unroll
+        for (int a = 0; a < 19; ++a) {
+            if constexpr (DEV) fa[a] = fmad(C(K * w19(a)), rho - own_rref, fs[a]);
+            else fa[a] = fs[a] + (a == 0 ? r0 : (a < 7 ? r1 : r2));
+        }
         auto fval = [&](int a, int slot, int dx, int dy) -> E {
             if constexpr (DEV) {
-                const C bd = ST::rdec(ST::renc(s_rho[slot][li + dy * EX + dx]));
-                return ST::enc(fmad((C)w19(a), rho - bd, fs[a]));
+                const C bd = rref(slot, li + dy * EX + dx);
+                return ST::enc(fmad(C(K * w19(a)), own_rref - bd, fa[a]));
             } else {
-                return ST::enc(fs[a] + (a == 0 ? r0 : (a < 7 ? r1 : r2)));
+                return ST::enc(fa[a]);
             }
         };
 #pragma unroll
@@ -704,7 +783,7 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
             const unsigned inrow = Yo[ey + 1] + Xo[ex + 1];
             if (WALLS) {
                 if (ez < 0 && z == 0) {  // Eq. (50): halfway bounce-back into the own node
-                    io.store(opposite(a), ownb, fval(a, s0, 0, 0));
+                    io.store(opposite(a), ownb, ST::enc(fa[a]));
                     continue;
                 }
                 if (ez > 0 && z == nz - 1) continue;  // leaves through the open top
@@ -713,22 +792,28 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
             }
             io.store(a, Zo[ez + 1] + inrow, fval(a, sl[ez + 1], ex, ey));
         }
-        // D3Q7: g+ = w T_emit + gs; deviation storage subtracts w T_r of the
-        // destination.  A destination in the reservoir layer receives w T_shell.
+        // D3Q7: g+ = w T_emit + gs; the deviation formats encode against the
+        // destination's T_r as above.  A destination in the reservoir layer
+        // receives w T_shell.
         const C wT = P.wT1 * T_emit, wT0 = T_emit - C(6) * wT;
         const C wS = P.wT1 * P.T_shell, wS0 = P.T_shell - C(6) * wS;
-        auto gfull_minus_ref = [&](int a, int slot, int dx, int dy, bool to_shell) -> C {
+        C ga[7];
+#pragma unroll
+        for (int a = 0; a < 7; ++a) {
+            if constexpr (DEV) ga[a] = fmad(K * (a == 0 ? P.wT0 : P.wT1), T_emit - own_tref, gs[a]);
+            else ga[a] = (a == 0 ? wT0 : wT) + gs[a];
+        }
+        auto gval = [&](int a, int slot, int dx, int dy, bool to_shell) -> C {
             if constexpr (DEV) {
-                const C bd = ST::rdec(ST::renc(s_tem[slot][li + dy * EX + dx]));
-                if (to_shell) return (a == 0 ? P.wT0 : P.wT1) * (P.T_shell - bd);
-                return fmad(a == 0 ? P.wT0 : P.wT1, T_emit - bd, gs[a]);
+                const C bd = s_tref[slot][li + dy * EX + dx];
+                const C wK = K * (a == 0 ? P.wT0 : P.wT1);
+                if (to_shell) return wK * (P.T_shell - bd);
+                return fmad(wK, own_tref - bd, ga[a]);
             } else {
                 if (to_shell) return a == 0 ? wS0 : wS;
-                return (a == 0 ? wT0 : wT) + gs[a];
+                return ga[a];
             }
         };
-        C own_tref = C(0);
-        if constexpr (DEV) own_tref = ST::rdec(ST::renc(T));
         if (P.thermal) {
 #pragma unroll
             for (int a = 0; a < 7; ++a) {
@@ -738,27 +823,26 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
                     const bool bottom = ez < 0 && z == 0, top = ez > 0 && z == nz - 1;
                     if (bottom || top) {
                         const C Tw = bottom ? T_bottom : (C)P.T_top;
-                        const C v = DEV ? fmad(P.wT1, C(2) * Tw - T - own_tref, -gs[a])
-                                        : fmad(C(2) * P.wT1, Tw, -gfull_minus_ref(a, s0, 0, 0, false));
+                        const C v = DEV ? fmad(K * P.wT1, C(2) * Tw - T - own_tref, -gs[a])
+                                        : fmad(C(2) * P.wT1, Tw, -ga[a]);
                         io.store(G0 + opposite(a), ownb, ST::enc(v));
                         continue;
                     }
                 }
                 const bool to_shell = xs[ex + 1] || ys[ey + 1] || zs[ez + 1];
-                io.store(G0 + a, Zo[ez + 1] + Yo[ey + 1] + Xo[ex + 1],
-                         ST::enc(gfull_minus_ref(a, sl[ez + 1], ex, ey, to_shell)));
+                io.store(G0 + a, Zo[ez + 1] + Yo[ey + 1] + Xo[ex + 1], ST::enc(gval(a, sl[ez + 1], ex, ey, to_shell)));
             }
         } else {
             // temperature held fixed: g stays at the node (re-encoded against the new reference)
 #pragma unroll
             for (int a = 0; a < 7; ++a) {
-                const C v = DEV ? fmad(a == 0 ? P.wT0 : P.wT1, nd.bt - own_tref, nd.r[a]) : nd.r[a];
+                const C v = DEV ? fmad(K * (a == 0 ? P.wT0 : P.wT1), nd.bt - own_tref, nd.r[a]) : nd.r[a];
                 io.store(G0 + a, ownb, ST::enc(v));
             }
         }
         if constexpr (DEV) {
-            io.store(RRHO, ownb, ST::renc(rho));
-            io.store(RT, ownb, ST::renc(T));
+            io.store_ref(0, own * RSZ, ST::renc(rho));
+            io.store_ref(1, own * RSZ, ST::renc(T));
         }
         if (P.gravity) rho_sum += (double)rho;
     };
@@ -820,7 +904,10 @@ struct NodeView {
     size_t st;
     __device__ double e(int a, size_t i) const { return ST::ddec(pop[a * st + i]); }
     __device__ double ref(int k, size_t i) const {
-        if constexpr (ST::kDev) return (double)ST::rdec(pop[(26 + k) * st + i]);
+        if constexpr (ST::kDev) {
+            const typename ST::R *refs = reinterpret_cast<const typename ST::R *>(pop + kPopPlanes * st);
+            return (double)ST::rdec(refs[k * st + i]);
+        }
         else return 0.0;
     }
 };
@@ -844,8 +931,9 @@ __global__ void __launch_bounds__(256) k_init(const double *__restrict__ stage, 
     if constexpr (ST::kDev) {
         br = (double)ST::rdec(ST::renc((float)rho));
         bt = (double)ST::rdec(ST::renc((float)T));
-        pop[26 * st + i] = ST::renc((float)rho);
-        pop[27 * st + i] = ST::renc((float)T);
+        typename ST::R *refs = reinterpret_cast<typename ST::R *>(pop + kPopPlanes * st);
+        refs[i] = ST::renc((float)rho);
+        refs[st + i] = ST::renc((float)T);
     }
 #pragma unroll
     for (int a = 0; a < 19; ++a) pop[a * st + i] = ST::denc(fl[a] - w19(a) * br);

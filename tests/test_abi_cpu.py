@@ -54,15 +54,17 @@ def test_arena_bytes_and_validation(lib):
 
 
 def test_arena_bytes_of_the_storage_formats(lib):
-    """Deviation formats hold 28 planes per copy (26 populations and the
-    rho_r, T_r references) of 2 bytes (f16, bf16) or 4 bytes (f32dev)."""
+    """Deviation formats hold 26 population planes of 2 bytes (f16, bf16) or
+    4 bytes (f32dev) and two reference planes (rho_r, T_r: FP16 for f16,
+    FP32 otherwise) per copy."""
     from paper_2201_06039_amd import lbm, workloads as W
     p = W.load("evaporation_128")["params"]
     n = 128 ** 3
     rest = 4 * n + 6 * 8 * n  # FP32 phi history + FP64 staging
-    for fmt, planes, es in (("f16", 28, 2), ("bf16", 28, 2), ("f32dev", 28, 4), ("f32", 26, 4)):
+    for fmt, es, refs in (("f16", 2, 2 * 2), ("bf16", 2, 2 * 4), ("f32dev", 4, 2 * 4), ("f32", 4, 0)):
+        copy = (26 * es + refs) * n
         b = lbm.arena_bytes(p, fmt)
-        assert 2 * planes * es * n + rest <= b < 2 * planes * es * n + rest + (1 << 22), fmt
+        assert 2 * copy + rest <= b < 2 * copy + rest + (1 << 22), fmt
     assert set(lbm.STORAGE_FORMATS) == {"f32", "f64", "f16", "bf16", "f32dev"}
 
 

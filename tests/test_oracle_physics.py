@@ -364,6 +364,33 @@ def test_spurious_current_order_of_magnitude(oracle_lib):
 # state
 # --------------------------------------------------------------------------
 
+@pytest.mark.slow
+def test_d2_law(oracle_lib):
+    """Sec. IV A: with the box boundary held at the vapour temperature, the
+    droplet's squared diameter falls linearly in time once the start-up
+    transient has passed.  32^3 box, D_0 = 20, T_sat droplet in T_sat + 0.14 T_c
+    vapour; over t = 3000..6000 a straight line must explain D^2 with
+    R^2 >= 0.999 while D^2 drops by more than a tenth of D_0^2.  (A mass loss
+    rate that were constant instead, D^3 linear in t, or evaporation stalling
+    as the vapour heats, bends D^2(t) visibly over this drop.)"""
+    import precision_metrics as PM
+    from paper_2201_06039_amd import workloads as W
+
+    def runner(w):
+        s = oracle_lib.Sim(**w["params"])
+        s.init_fields(*W.fields(w))
+        return s.step, s.rho_u_T, s.close
+
+    r = PM.run_case("d2", runner)
+    t, d2 = np.asarray(r["times"], float), np.asarray(r["d2"], float)
+    c = np.polyfit(t, d2, 1)
+    res = d2 - np.polyval(c, t)
+    r2 = 1.0 - (res ** 2).sum() / ((d2 - d2.mean()) ** 2).sum()
+    assert c[0] < 0
+    assert d2[0] - d2[-1] > 0.1
+    assert r2 >= 0.999, r2
+
+
 def test_checkpoint_continuation_is_bitwise(oracle_lib):
     """f, g, phi_s(t - dt) and rho_ave are the whole state: run(2n) equals
     run(n) + save + restore into a fresh simulation + run(n), bit for bit."""
