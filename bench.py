@@ -1,12 +1,17 @@
 """Benchmark of the fused D3Q19 + D3Q7 thermal pseudopotential LB step.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                    [--storage f32|f64|f16|bf16|f32dev] [--tile TXxTY] [--chunk CZ] [--no-cpu-baseline]
+                    [--storage f16|f32|f64|bf16|f32dev] [--compare f32|none]
+                    [--tile TXxTY] [--chunk CZ] [--no-precision] [--no-cpu-baseline]
 
 One step = one fused time step of the whole grid (both lattices, streaming and
 boundary rules) on synthetic seeded input already resident in HBM.  Prints one
-JSON line: MLUPS (million lattice-node updates per second), the HBM roofline
-of the step kernel and the FP64 oracle timed on the host as a CPU baseline.
+JSON line: MLUPS (million lattice-node updates per second) of the chosen
+population storage (FP16 deviations by default), the HBM roofline of the step
+kernel, the same step with FP32 storage for comparison, the errors of the
+storage format against the FP64 oracle's reference values (coexistence
+densities, Laplace jump, D^2 slope), and the FP64 oracle timed on the host as
+a CPU baseline.
 """
 import argparse
 import hashlib
@@ -26,8 +31,12 @@ HBM_PEAK_GBS = 8000.0
 # once and written once.
 BYTES_PER_LUP = {"f32": 2 * 26 * 4 + 8, "f64": 2 * 26 * 8 + 16, "f16": 2 * (26 * 2 + 2 * 2) + 8,
                  "bf16": 2 * (26 * 2 + 2 * 4) + 8, "f32dev": 2 * 28 * 4 + 8}
+PRECISION_BOUND = 1e-3
 KERNEL_SOURCES = ["paper_2201_06039_amd/csrc/lbm_kernels.hpp", "paper_2201_06039_amd/csrc/lbm_api.hip"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_evaporation_128_traffic.json")
+
+
+def traffic_file(workload, storage):
+    return os.path.join(ROOT, "profiles", f"k_step_{workload}_{storage}_traffic.json")
 
 
 def kernel_hash():
@@ -42,7 +51,7 @@ def measured_traffic(workload, storage, launch):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source with the same workload and launch."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(traffic_file(workload, storage)) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -75,15 +84,64 @@ def cpu_baseline(w, fields, seconds=15.0):
                       f"after 1 untimed step, FP64 C + OpenMP"}
 
 
+def timed_run(lbm, p, fields, storage, steps, warmup, tile=None, chunk=None):
+    """Warm up, then time `steps` steps with HIP events on the library's stream."""
+    import torch
+    lat = lbm.Lattice(p, storage=storage, device="cuda:0")
+    if tile or chunk:
+        cur = lat.launch()
+        tx, ty = (int(v) for v in tile.split("x")) if tile else (cur["tile_x"], cur["tile_y"])
+        lat.set_launch(tx, ty, chunk or cur["chunk_z"])
+    launch = lat.launch()
+    lat.init_fields(*fields)
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(lat.stream)
+    lat.step(steps)
+    end.record(lat.stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    lat.rho_u_T()  # raises if any step was unstable
+    launches = lat.launches_per_step()
+    lat.close()
+    return ms, launch, launches
+
+
+def precision_errors(storage):
+    """Relative errors of the coexistence densities, Laplace jump and D^2
+    slope of a run with this storage against the FP64 oracle's values
+    (stored in tests/golden/precision_refs.json by the oracle)."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import precision_metrics as PM
+    from paper_2201_06039_amd import lbm, workloads as W
+    with open(os.path.join(ROOT, "tests", "golden", "precision_refs.json")) as fh:
+        refs = json.load(fh)["cases"]
+
+    def make(w):
+        lat = lbm.Lattice(w["params"], storage=storage, device="cuda:0")
+        lat.init_fields(*W.fields(w))
+        return lat.step, lat.rho_u_T, lat.close
+
+    out = {}
+    for case in PM.CASES:
+        for k, v in PM.relative_errors(case, PM.run_case(case, make), refs[case]).items():
+            out[f"{case}_{k}"] = float(f"{v:.3e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="evaporation_128")
-    ap.add_argument("--storage", default="f32", choices=sorted(BYTES_PER_LUP))
+    ap.add_argument("--storage", default="f16", choices=sorted(BYTES_PER_LUP))
+    ap.add_argument("--compare", default="f32", choices=sorted(BYTES_PER_LUP) + ["none"],
+                    help="second storage format timed on the same workload")
     ap.add_argument("--tile", default=None, help="TXxTY, e.g. 64x4")
     ap.add_argument("--chunk", type=int, default=None)
+    ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="only run 20 plain device-to-device copies of MB megabytes (to calibrate the "
@@ -121,35 +179,17 @@ def main():
     p = w["params"]
     nn = p["nx"] * p["ny"] * p["nz"]
 
-    lat = lbm.Lattice(p, storage=args.storage, device="cuda:0")
-    if args.tile or args.chunk:
-        cur = lat.launch()
-        tx, ty = (int(v) for v in args.tile.split("x")) if args.tile else (cur["tile_x"], cur["tile_y"])
-        lat.set_launch(tx, ty, args.chunk or cur["chunk_z"])
-    launch = lat.launch()
-    lat.init_fields(*fields)
-    print(f"# workload {args.workload} {p['nx']}x{p['ny']}x{p['nz']} storage {args.storage} launch {launch}",
-          file=sys.stderr, flush=True)
-
-    lat.step(args.warmup)
-    torch.cuda.synchronize()
-    stream = lat.stream
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    lat.step(args.steps)
-    end.record(stream)
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(end)
-    # any instability during the timed steps fails the run
-    rho, ux, uy, uz, T = lat.rho_u_T()
+    print(f"# workload {args.workload} {p['nx']}x{p['ny']}x{p['nz']} storage {args.storage}", file=sys.stderr,
+          flush=True)
+    ms, launch, launches = timed_run(lbm, p, fields, args.storage, args.steps, args.warmup, args.tile, args.chunk)
+    print(f"# {args.storage}: {ms / args.steps:.5f} ms/step, launch {launch}", file=sys.stderr, flush=True)
 
     sec = ms / 1e3
     mlups = nn * args.steps / sec / 1e6
-    launches = lat.launches_per_step()
     avg_launch_s = sec / args.steps  # the step kernel is the only launch per step when launches == 1
     bytes_alg = BYTES_PER_LUP[args.storage] * nn
     achieved = bytes_alg / avg_launch_s / 1e9
-    traffic = measured_traffic(args.workload, args.storage, launch)
+    arith = "f64" if args.storage == "f64" else "f32"
     out = {
         "metric": METRIC,
         "value": round(mlups, 2),
@@ -161,16 +201,31 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.storage,
+        "dtype": arith,
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": [p["nx"], p["ny"], p["nz"]], "storage": args.storage,
                    "tile": [launch["tile_x"], launch["tile_y"]], "chunk_z": launch["chunk_z"],
                    "workgroups": launch["workgroups"], "launches_per_step": launches},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(args.workload, args.storage, launch),
                      "kernel": "k_step", "bytes_per_lup": BYTES_PER_LUP[args.storage]},
     }
-    lat.close()
+    if args.compare != "none" and args.compare != args.storage:
+        ms2, launch2, _ = timed_run(lbm, p, fields, args.compare, args.steps, args.warmup)
+        print(f"# {args.compare}: {ms2 / args.steps:.5f} ms/step, launch {launch2}", file=sys.stderr, flush=True)
+        sec2 = ms2 / 1e3 / args.steps
+        out["compare"] = {"storage": args.compare, "value": round(nn / sec2 / 1e6, 2), "unit": "MLUPS",
+                          "ms_per_step": round(ms2 / args.steps, 5),
+                          "roofline_frac": round(BYTES_PER_LUP[args.compare] * nn / sec2 / 1e9 / HBM_PEAK_GBS, 4),
+                          "bytes_per_lup": BYTES_PER_LUP[args.compare],
+                          "tile": [launch2["tile_x"], launch2["tile_y"]], "chunk_z": launch2["chunk_z"],
+                          "speedup_of_storage": round(ms2 / ms, 3)}
+    if not args.no_precision:
+        errs = precision_errors(args.storage)
+        print(f"# precision of {args.storage}: {errs}", file=sys.stderr, flush=True)
+        out["precision"] = {"storage": args.storage, "reference": "FP64 oracle", "bound": PRECISION_BOUND,
+                            "relative_errors": errs, "within_bound": max(errs.values()) <= PRECISION_BOUND}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, fields)
     print(json.dumps(out), flush=True)

@@ -212,7 +212,13 @@ int hip_status(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EHIP; }
 // workgroups than the 256 compute units.
 void set_default_launch(lbm_handle *h) {
     const int nx = h->p.nx, ny = h->p.ny, nz = h->p.nz;
-    if (nx >= 96) {
+    const bool half = h->L.es == 2;
+    if (half && nx >= 64) {
+        // 16-bit storage: the kernel is bound by instruction issue more than
+        // by the row length, and 64x8 tiles recompute fewer halo nodes.
+        h->tile_x = 64;
+        h->tile_y = 8;
+    } else if (nx >= 96) {
         h->tile_x = 128;
         h->tile_y = 4;
     } else if (nx > 32) {

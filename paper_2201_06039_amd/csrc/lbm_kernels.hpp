@@ -341,9 +341,11 @@ constexpr int kPopPlanes = 26;
 // Access to the planes of the two ping-pong copies.  A copy holds 26
 // population planes of T, `stride` elements apart, then (deviation formats)
 // the rho_r and T_r planes of R, `stride` elements apart.
+// Every access names a plane, a per-thread byte offset `v` (the node's place
+// inside an x-y plane) and a workgroup-uniform byte offset `s` (the z plane).
 //  BUF = true: two buffer resources per copy (planes below plane 14, and the
-//  rest); a plane's offset is a scalar and the node's byte offset one 32-bit
-//  vector offset shared by all planes, so loads cost no vector address
+//  rest); the plane and z offsets go into the scalar offset, the x-y offset
+//  is the one vector offset, so loads and stores cost no vector address
 //  arithmetic.  Needs each half to span less than 4 GiB.
 //  BUF = false: plain global pointers (any size).
 template <typename T, typename R, bool BUF>
@@ -362,20 +364,20 @@ struct PopIO<T, R, true> {
         out_lo = __builtin_amdgcn_make_buffer_rsrc(pout, 0, -1, kBufferFlags);
         out_hi = __builtin_amdgcn_make_buffer_rsrc(pout + kSplitPlane * stride, 0, -1, kBufferFlags);
     }
-    __device__ T load(int a, unsigned boff) const {
-        return a < kSplitPlane ? buf_ld<T>(in_lo, boff, (unsigned)a * sb)
-                               : buf_ld<T>(in_hi, boff, (unsigned)(a - kSplitPlane) * sb);
+    __device__ T load(int a, unsigned v, unsigned s) const {
+        return a < kSplitPlane ? buf_ld<T>(in_lo, v, (unsigned)a * sb + s)
+                               : buf_ld<T>(in_hi, v, (unsigned)(a - kSplitPlane) * sb + s);
     }
-    __device__ void store(int a, unsigned boff, T v) const {
-        if (a < kSplitPlane) buf_st<T>(v, out_lo, boff, (unsigned)a * sb);
-        else buf_st<T>(v, out_hi, boff, (unsigned)(a - kSplitPlane) * sb);
+    __device__ void store(int a, unsigned v, unsigned s, T x) const {
+        if (a < kSplitPlane) buf_st<T>(x, out_lo, v, (unsigned)a * sb + s);
+        else buf_st<T>(x, out_hi, v, (unsigned)(a - kSplitPlane) * sb + s);
     }
-    // reference plane k (0: rho_r, 1: T_r); rboff = node index * sizeof(R)
-    __device__ R load_ref(int k, unsigned rboff) const {
-        return buf_ld<R>(in_hi, rboff, (unsigned)(kPopPlanes - kSplitPlane) * sb + (unsigned)k * rsb);
+    // reference plane k (0: rho_r, 1: T_r); offsets in units of sizeof(R)
+    __device__ R load_ref(int k, unsigned v, unsigned s) const {
+        return buf_ld<R>(in_hi, v, (unsigned)(kPopPlanes - kSplitPlane) * sb + (unsigned)k * rsb + s);
     }
-    __device__ void store_ref(int k, unsigned rboff, R v) const {
-        buf_st<R>(v, out_hi, rboff, (unsigned)(kPopPlanes - kSplitPlane) * sb + (unsigned)k * rsb);
+    __device__ void store_ref(int k, unsigned v, unsigned s, R x) const {
+        buf_st<R>(x, out_hi, v, (unsigned)(kPopPlanes - kSplitPlane) * sb + (unsigned)k * rsb + s);
     }
 };
 
@@ -385,19 +387,19 @@ struct PopIO<T, R, false> {
     T *out;
     size_t st;
     __device__ PopIO(const T *pin, T *pout, size_t stride) : in(pin), out(pout), st(stride) {}
-    __device__ T load(int a, unsigned boff) const {
-        return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(in + a * st) + boff);
+    __device__ T load(int a, unsigned v, unsigned s) const {
+        return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(in + a * st) + s + v);
     }
-    __device__ void store(int a, unsigned boff, T v) const {
-        *reinterpret_cast<T *>(reinterpret_cast<char *>(out + a * st) + boff) = v;
+    __device__ void store(int a, unsigned v, unsigned s, T x) const {
+        *reinterpret_cast<T *>(reinterpret_cast<char *>(out + a * st) + s + v) = x;
     }
-    __device__ R load_ref(int k, unsigned rboff) const {
+    __device__ R load_ref(int k, unsigned v, unsigned s) const {
         const R *base = reinterpret_cast<const R *>(in + kPopPlanes * st) + k * st;
-        return *reinterpret_cast<const R *>(reinterpret_cast<const char *>(base) + rboff);
+        return *reinterpret_cast<const R *>(reinterpret_cast<const char *>(base) + s + v);
     }
-    __device__ void store_ref(int k, unsigned rboff, R v) const {
+    __device__ void store_ref(int k, unsigned v, unsigned s, R x) const {
         R *base = reinterpret_cast<R *>(out + kPopPlanes * st) + k * st;
-        *reinterpret_cast<R *>(reinterpret_cast<char *>(base) + rboff) = v;
+        *reinterpret_cast<R *>(reinterpret_cast<char *>(base) + s + v) = x;
     }
 };
 
@@ -452,7 +454,19 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
     __shared__ C s_tref[TS][TN];  // the references every node writes for itself
     __shared__ double s_red[NT / 64];
 
-    const Phys<C> &P = A.P;
+    // The float constants of the model are read by vector instructions in
+    // every iteration; held in scalar registers they exceed the scalar
+    // register file and are spilled to vector lanes, costing one read per use.
+    // Keeping them in vector registers from the start (the empty asm only
+    // tells the compiler they live there) avoids that.
+    Phys<C> P = A.P;
+    if constexpr (sizeof(C) == 4) {
+        C *v[] = {&P.a, &P.b, &P.R, &P.kap, &P.inv_Tc, &P.two_over_Gc2, &P.negG, &P.sig6, &P.lam_e, &P.lam_v,
+                  &P.lam_q, &P.lam_pi, &P.divu_a, &P.divu_b, &P.inv_cV, &P.wT0, &P.wT1, &P.inv_csT2, &P.kappa,
+                  &P.gam_q, &P.gam_pi, &P.gx, &P.gy, &P.gz, &P.T_shell};
+#pragma unroll
+        for (C *q : v) asm("" : "+v"(*q));
+    }
     const int nx = A.nx, ny = A.ny, nz = A.nz;
     const unsigned plane = (unsigned)nx * (unsigned)ny;
     const PopIO<E, typename ST::R, BUF> io(A.pop_in, A.pop_out, A.stride);
@@ -496,15 +510,15 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
         return zz < 0 ? zz + nz : zz;
     };
 
-    auto load_node = [&](unsigned node, NodePops<C> &n) {
-        const unsigned b = node * ES;
+    // Node `row` (index inside an x-y plane) of the plane starting at node zoff.
+    auto load_node = [&](unsigned row, unsigned zoff, NodePops<C> &n) {
 #pragma unroll
-        for (int a = 0; a < 19; ++a) n.e[a] = ST::dec(io.load(a, b));
+        for (int a = 0; a < 19; ++a) n.e[a] = ST::dec(io.load(a, row * ES, zoff * ES));
 #pragma unroll
-        for (int a = 0; a < 7; ++a) n.r[a] = ST::dec(io.load(G0 + a, b));
+        for (int a = 0; a < 7; ++a) n.r[a] = ST::dec(io.load(G0 + a, row * ES, zoff * ES));
         if constexpr (DEV) {
-            n.br = ST::rdec(io.load_ref(0, node * RSZ));
-            n.bt = ST::rdec(io.load_ref(1, node * RSZ));
+            n.br = ST::rdec(io.load_ref(0, row * RSZ, zoff * RSZ));
+            n.bt = ST::rdec(io.load_ref(1, row * RSZ, zoff * RSZ));
         } else {
             n.br = C(0);
             n.bt = C(0);
@@ -513,8 +527,8 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
     // State of plane zp for this thread's tile node and its halo node.
     auto load_plane = [&](int zp, NodePops<C> &k, NodePops<C> &h) {
         const unsigned zoff = (unsigned)zmap(zp) * plane;
-        load_node(zoff + irow, k);
-        if (has_halo) load_node(zoff + hrow, h);
+        load_node(irow, zoff, k);
+        if (has_halo) load_node(hrow, zoff, h);
     };
 
     // rho = rho_r + sum e / K and T = T_r + sum r / K of a loaded node.
@@ -745,7 +759,7 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
             Zo[1] = Zc;
             Zo[2] = (unsigned)(z == nz - 1 ? 0 : z + 1) * PB;
         }
-        const unsigned ownb = own * ES;
+        const unsigned rowb = irow * ES;
         // Values stored for the D3Q19 population a bound for the node in ring
         // slot `slot` at offset (dx, dy).  Plain storage keeps f* (the rest
         // part r0 closes the sum exactly: the rounded 1/3 + 6/18 + 12/36 is
@@ -783,14 +797,14 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
             const unsigned inrow = Yo[ey + 1] + Xo[ex + 1];
             if (WALLS) {
                 if (ez < 0 && z == 0) {  // Eq. (50): halfway bounce-back into the own node
-                    io.store(opposite(a), ownb, ST::enc(fa[a]));
+                    io.store(opposite(a), rowb, Zc, ST::enc(fa[a]));
                     continue;
                 }
                 if (ez > 0 && z == nz - 1) continue;  // leaves through the open top
                 if (ez < 0 && z == nz - 1)             // open top: unknown f copied from below
-                    io.store(a, Zc + inrow, fval(a, s0, ex, ey));
+                    io.store(a, inrow, Zc, fval(a, s0, ex, ey));
             }
-            io.store(a, Zo[ez + 1] + inrow, fval(a, sl[ez + 1], ex, ey));
+            io.store(a, inrow, Zo[ez + 1], fval(a, sl[ez + 1], ex, ey));
         }
         // D3Q7: g+ = w T_emit + gs; the deviation formats encode against the
         // destination's T_r as above.  A destination in the reservoir layer
@@ -825,24 +839,24 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
                         const C Tw = bottom ? T_bottom : (C)P.T_top;
                         const C v = DEV ? fmad(K * P.wT1, C(2) * Tw - T - own_tref, -gs[a])
                                         : fmad(C(2) * P.wT1, Tw, -ga[a]);
-                        io.store(G0 + opposite(a), ownb, ST::enc(v));
+                        io.store(G0 + opposite(a), rowb, Zc, ST::enc(v));
                         continue;
                     }
                 }
                 const bool to_shell = xs[ex + 1] || ys[ey + 1] || zs[ez + 1];
-                io.store(G0 + a, Zo[ez + 1] + Yo[ey + 1] + Xo[ex + 1], ST::enc(gval(a, sl[ez + 1], ex, ey, to_shell)));
+                io.store(G0 + a, Yo[ey + 1] + Xo[ex + 1], Zo[ez + 1], ST::enc(gval(a, sl[ez + 1], ex, ey, to_shell)));
             }
         } else {
             // temperature held fixed: g stays at the node (re-encoded against the new reference)
 #pragma unroll
             for (int a = 0; a < 7; ++a) {
                 const C v = DEV ? fmad(K * (a == 0 ? P.wT0 : P.wT1), nd.bt - own_tref, nd.r[a]) : nd.r[a];
-                io.store(G0 + a, ownb, ST::enc(v));
+                io.store(G0 + a, rowb, Zc, ST::enc(v));
             }
         }
         if constexpr (DEV) {
-            io.store_ref(0, own * RSZ, ST::renc(rho));
-            io.store_ref(1, own * RSZ, ST::renc(T));
+            io.store_ref(0, irow * RSZ, (unsigned)z * plane * RSZ, ST::renc(rho));
+            io.store_ref(1, irow * RSZ, (unsigned)z * plane * RSZ, ST::renc(T));
         }
         if (P.gravity) rho_sum += (double)rho;
     };

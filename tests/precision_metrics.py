@@ -10,7 +10,6 @@ import copy
 
 import numpy as np
 
-from oracle import thermo
 from paper_2201_06039_amd import workloads as W
 
 CASES = {
@@ -52,13 +51,23 @@ def slab_densities(rho, p):
     return float(prof.max()), float(prof.min())
 
 
+def pressure(rho, T, p):
+    """Peng-Robinson pressure of Eq. (49), a = 0.45724 R^2 Tc^2/pc and
+    b = 0.0778 R Tc/pc giving Tc = (0.0778/0.45724) a/(b R)."""
+    a, b, R, w = p["a"], p["b"], p["R"], p["acentric"]
+    Tc = 0.0778 / 0.45724 * a / (b * R)
+    kap = 0.37464 + 1.54226 * w - 0.26992 * w * w
+    th = (1.0 + kap * (1.0 - np.sqrt(T / Tc))) ** 2
+    return rho * R * T / (1.0 - b * rho) - a * th * rho * rho / (1.0 + 2.0 * b * rho - b * b * rho * rho)
+
+
 def laplace_jump(rho, T, p):
-    """p_EOS at the droplet centre minus p_EOS at the box corner (Eq. (49))."""
+    """p_EOS at the droplet centre minus p_EOS at the box corner."""
     n = rho.reshape(p["nz"], p["ny"], p["nx"])
     t = T.reshape(p["nz"], p["ny"], p["nx"])
     c = (p["nz"] // 2, p["ny"] // 2, p["nx"] // 2)
-    pin = thermo.pressure(n[c], t[c], p["a"], p["b"], p["R"], p["acentric"])
-    pout = thermo.pressure(n[0, 0, 0], t[0, 0, 0], p["a"], p["b"], p["R"], p["acentric"])
+    pin = pressure(n[c], t[c], p)
+    pout = pressure(n[0, 0, 0], t[0, 0, 0], p)
     return float(pin - pout), float(n[c]), float(n[0, 0, 0])
 
 

@@ -157,3 +157,52 @@ def test_thermal_reservoir_boundary_fp64(launch):
     for face in (T[0], T[-1], T[:, 0], T[:, -1], T[:, :, 0], T[:, :, -1]):
         assert np.abs(face - Ts).max() <= 1e-14 * Ts
 
+
+
+# Deviation formats.  f32dev is held to the FP32 bar.  For the 16-bit formats
+# the bar on rho and T is one rounding of the field itself in the storage
+# type (2^-11 for FP16, 2^-8 for BF16): storing deviations must never be worse
+# than storing the density or temperature in that type.  u, a small difference
+# of O(rho) momenta, is held in the L2 sense to 20 such roundings.
+DEV_TOL = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}
+
+DEV_CASES = [
+    ("static_droplet_32", {}, 300),
+    ("evaporation_128", dict(nx=40, ny=40, nz=40, radius=9.0), 60),
+    ("pool_boiling_32x32x48", {}, 50),
+    ("flat_interface_128", dict(nx=3, ny=2, nz=64), 200),
+    ("d2_law_48", dict(nx=26, ny=22, nz=20, radius=6.0), 60),
+]
+
+
+@pytest.mark.parametrize("case", DEV_CASES, ids=[c[0] for c in DEV_CASES])
+@pytest.mark.parametrize("storage", ["f32dev", "f16", "bf16"])
+def test_deviation_storage_against_oracle(storage, case):
+    name, ov, steps = case
+    w = workload(name, **ov)
+    _say(f"{name} {ov} {storage} steps={steps}")
+    ref = run_oracle(w, steps)
+    e = errors(run_gpu(w, steps, storage), ref)
+    if storage == "f32dev":
+        tu = fp32_u_tol(steps, ref)
+        _say(f"  errors {e} u-tolerance {tu:.3e}")
+        _check(e, FP32_TOL, tol_u=tu)
+    else:
+        tol = DEV_TOL[storage]
+        _say(f"  errors {e} tolerance {tol:.3e}")
+        assert e["rho"] <= tol and e["T"] <= tol, e
+        assert e["u_l2"] <= 20 * tol, e
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16", "f32dev"])
+def test_deviation_storage_launch_shape_bitwise(storage):
+    """The deviation encode reads the destination's reference from the LDS
+    ring; every launch shape must still compute each node identically."""
+    w = workload("evaporation_128", nx=40, ny=36, nz=20, radius=7.0)
+    outs = []
+    for launch in [(64, 8, 4), (32, 8, 7), (128, 4, 20), (32, 16, 1)]:
+        _say(f"{storage} launch {launch}")
+        outs.append(run_gpu(w, 25, storage, launch=launch))
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
