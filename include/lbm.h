@@ -173,6 +173,68 @@ void lbm_destroy(lbm_handle *h);
 /* Static description of a status code. */
 const char *lbm_strerror(int status);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many independent lattices (each its own lbm_params: grid, EOS
+ * constants, temperatures, relaxation times) advanced together, one launch
+ * per time step for all of them.  Each lattice follows exactly the time step
+ * of a single lattice (the calls above), and its results are bitwise those of
+ * a single lattice run with the same tile shape.  The launch is persistent: a
+ * fixed grid of workgroups takes (lattice, tile, z-chunk) items from a device
+ * work counter, largest lattices first, so lattices of uneven size share the
+ * GPU.  On a non-NULL stream, lbm_batch_step() replays a captured HIP graph of
+ * two steps.
+ *
+ * Restrictions (EINVAL otherwise): 1 <= ncases <= 65536, every lattice valid
+ * for lbm_create, the same `storage` for all, bc_z = LBM_BC_PERIODIC, no
+ * gravity (g = 0; the reservoir boundary bc_T_shell is allowed).
+ * --------------------------------------------------------------------------- */
+typedef struct lbm_batch lbm_batch;
+
+/* Device bytes of a batch arena for these lattices (0 if invalid): each
+ * lattice's two population copies, phi_s plane and scalars, plus one set of
+ * staging planes and partial sums sized for the largest lattice, the work
+ * list and its counter, per-lattice step descriptors, and a copy of every
+ * phi_s plane for lbm_batch_autotune(). */
+size_t lbm_batch_arena_bytes(const lbm_params *cases, int ncases);
+
+/* Carve the caller-owned arena (256-byte aligned) and bind the stream.  The
+ * launch starts at the default tile of the largest lattice's format.
+ * EINVAL / ENOMEM as for lbm_create. */
+int lbm_batch_create(const lbm_params *cases, int ncases, void *dev_arena, size_t arena_bytes, void *hip_stream,
+                     lbm_batch **out);
+
+/* Initial state of lattice c (0 <= c < ncases) from FP64 host fields, as
+ * lbm_init_fields.  Every lattice must be initialised before lbm_batch_step. */
+int lbm_batch_init_case(lbm_batch *b, int c, const double *rho, const double *ux, const double *uy,
+                        const double *uz, const double *T);
+
+/* Enqueue n >= 0 time steps of every lattice without blocking.  ESTATE if a
+ * lattice is not initialised. */
+int lbm_batch_step(lbm_batch *b, int n);
+
+/* Readout and sums of lattice c, as lbm_get_rho_u_T and lbm_reduce
+ * (EUNSTABLE reports a problem in lattice c since its last check). */
+int lbm_batch_get_rho_u_T(lbm_batch *b, int c, double *rho, double *ux, double *uy, double *uz, double *T);
+int lbm_batch_reduce(lbm_batch *b, int c, double *mass, double *energy);
+
+/* Launch shape shared by all lattices: tile (as lbm_set_launch), z-chunk
+ * length (clamped to each lattice's nz) and the number of persistent
+ * workgroups (0: two per compute unit's worth of resident 256-thread groups;
+ * at most the number of work items is used).  EINVAL for unsupported shapes. */
+int lbm_batch_set_launch(lbm_batch *b, int tile_x, int tile_y, int chunk_z, int workgroups);
+int lbm_batch_get_launch(const lbm_batch *b, int *tile_x, int *tile_y, int *chunk_z, int *workgroups, int *items);
+
+/* Autotuner: times `steps` launches of each candidate launch shape (every
+ * supported tile, chunks of 8, 16 and 32 planes, one and two persistent
+ * groups per compute unit) on the current state, keeps the fastest, and
+ * restores the state (the timed launches only write the idle population copy
+ * and the phi_s planes, which are put back).  *best_ms receives its time per
+ * step.  Synchronises the stream. */
+int lbm_batch_autotune(lbm_batch *b, int steps, double *best_ms);
+
+/* Release host resources (graphs included); the arena stays with the caller. */
+void lbm_batch_destroy(lbm_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,6 +7,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "lbm.h"
 #include "lbm_kernels.hpp"
 
@@ -186,19 +189,22 @@ struct lbm_handle {
     lbm_params p;
     Layout L;
     hipStream_t stream;
-    char *arena;
+    // Device regions: a lattice of its own has them all in its arena; the
+    // lattices of a batch share the staging planes and partial sums.
+    char *r_pop[2], *r_phi, *r_scal;
+    double *r_stage, *r_part;
     int cur;          // which population copy holds the state
     int initialized;
     int tile_x, tile_y, chunk_z;
     int workgroups;
-    unsigned *status() { return (unsigned *)(arena + L.off_scal + 8 * sizeof(double)); }
-    double *rho_ave() { return (double *)(arena + L.off_scal); }
-    double *mass() { return (double *)(arena + L.off_scal + sizeof(double)); }
-    double *energy() { return (double *)(arena + L.off_scal + 2 * sizeof(double)); }
-    double *stage() { return (double *)(arena + L.off_stage); }
-    double *partials() { return (double *)(arena + L.off_part); }
-    void *pop(int k) { return arena + L.off_pop[k]; }
-    void *phi() { return arena + L.off_phi; }
+    unsigned *status() { return (unsigned *)(r_scal + 8 * sizeof(double)); }
+    double *rho_ave() { return (double *)r_scal; }
+    double *mass() { return (double *)(r_scal + sizeof(double)); }
+    double *energy() { return (double *)(r_scal + 2 * sizeof(double)); }
+    double *stage() { return r_stage; }
+    double *partials() { return r_part; }
+    void *pop(int k) { return r_pop[k]; }
+    void *phi() { return r_phi; }
 };
 
 namespace {
@@ -363,7 +369,13 @@ int lbm_create(const lbm_params *p, void *dev_arena, size_t arena_bytes, void *h
     h->p = *p;
     h->L = L;
     h->stream = (hipStream_t)hip_stream;
-    h->arena = (char *)dev_arena;
+    char *arena = (char *)dev_arena;
+    h->r_pop[0] = arena + L.off_pop[0];
+    h->r_pop[1] = arena + L.off_pop[1];
+    h->r_phi = arena + L.off_phi;
+    h->r_scal = arena + L.off_scal;
+    h->r_stage = (double *)(arena + L.off_stage);
+    h->r_part = (double *)(arena + L.off_part);
     h->cur = 0;
     h->initialized = 0;
     set_default_launch(h);
@@ -377,9 +389,13 @@ int lbm_create(const lbm_params *p, void *dev_arena, size_t arena_bytes, void *h
     return LBM_OK;
 }
 
-int lbm_init_fields(lbm_handle *h, const double *rho, const double *ux, const double *uy, const double *uz,
-                    const double *T) {
-    if (!h || !rho || !ux || !uy || !uz || !T) return LBM_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// Initial state into population copy `copy` (which then holds the state).
+int init_state(lbm_handle *h, const double *rho, const double *ux, const double *uy, const double *uz,
+               const double *T, int copy) {
     const size_t nn = h->L.nn, bytes = nn * sizeof(double);
     double *st = h->stage();
     const double *src[5] = {rho, ux, uy, uz, T};
@@ -391,11 +407,11 @@ int lbm_init_fields(lbm_handle *h, const double *rho, const double *ux, const do
     if (rc) return rc;
     const lbm::Phys<double> P = make_phys<double>(&h->p);
     const int nb = (int)((nn + 255) / 256);
-    h->cur = 0;
+    h->cur = copy;
     rc = with_format(h->p.storage, [&](auto fmt) {
         using ST = decltype(fmt);
         hipLaunchKernelGGL(lbm::k_init<ST>, dim3(nb), dim3(256), 0, h->stream, (const double *)st, nn,
-                           (typename ST::T *)h->pop(0), (typename ST::C *)h->phi(), h->L.stride, P, h->status());
+                           (typename ST::T *)h->pop(copy), (typename ST::C *)h->phi(), h->L.stride, P, h->status());
         return reduce_state<ST>(h, true);
     });
     if (rc) return rc;
@@ -409,6 +425,16 @@ int lbm_init_fields(lbm_handle *h, const double *rho, const double *ux, const do
     }
     h->initialized = 1;
     return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_init_fields(lbm_handle *h, const double *rho, const double *ux, const double *uy, const double *uz,
+                    const double *T) {
+    if (!h || !rho || !ux || !uy || !uz || !T) return LBM_EINVAL;
+    return init_state(h, rho, ux, uy, uz, T, 0);
 }
 
 int lbm_step(lbm_handle *h, int n) {
@@ -592,6 +618,434 @@ const char *lbm_strerror(int status) {
     case LBM_ESTATE: return "call out of order";
     }
     return "unknown status";
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches of independent lattices.
+// ---------------------------------------------------------------------------
+
+struct lbm_batch {
+    int n;
+    int storage;
+    hipStream_t stream;
+    lbm_handle *cases;     // per-lattice handles (regions inside the batch arena)
+    int *order;            // lattices by decreasing node count (work-list order)
+    // shared device regions
+    char *d_desc;          // StepArgs of every lattice
+    unsigned *d_item_case, *d_first_item, *d_queue;
+    char *d_phi_backup;    // copy of all phi_s planes (autotuner)
+    size_t max_items;
+    int cus;               // compute units of the device
+    // launch
+    int tile_x, tile_y, chunk_z, workgroups;
+    unsigned n_items;
+    int cur;               // population copy holding the state of every lattice
+    hipGraphExec_t exec[2];  // two steps starting from copy 0 / copy 1
+};
+
+namespace {
+
+constexpr size_t kDescBytes = sizeof(lbm::StepArgs<lbm::StoreF64>) > sizeof(lbm::StepArgs<lbm::StoreF32>)
+                                  ? sizeof(lbm::StepArgs<lbm::StoreF64>)
+                                  : sizeof(lbm::StepArgs<lbm::StoreF32>);
+
+bool valid_batch(const lbm_params *cases, int n) {
+    if (!cases || n < 1 || n > 65536) return false;
+    for (int c = 0; c < n; ++c) {
+        const lbm_params *p = cases + c;
+        if (!valid_params(p) || p->storage != cases[0].storage || p->bc_z != LBM_BC_PERIODIC) return false;
+        if (p->g[0] != 0.0 || p->g[1] != 0.0 || p->g[2] != 0.0) return false;
+    }
+    return true;
+}
+
+// Per-lattice regions: two copies, phi_s, scalars.
+size_t case_bytes(const Layout &L) {
+    return 2 * align_up(copy_bytes(L), kAlign) + align_up(L.stride * L.cs, kAlign) + align_up(64 * sizeof(double), kAlign);
+}
+
+struct BatchLayout {
+    size_t off_stage, off_part, off_queue, off_desc, off_item_case, off_first, off_phi_backup, off_cases, total;
+    size_t max_items;
+};
+
+BatchLayout make_batch_layout(const lbm_params *cases, int n) {
+    BatchLayout B;
+    size_t max_nn = 0, max_part = 0, items = 0, phi = 0, lat = 0;
+    for (int c = 0; c < n; ++c) {
+        const Layout L = make_layout(cases + c);
+        max_nn = L.nn > max_nn ? L.nn : max_nn;
+        max_part = L.max_partials > max_part ? L.max_partials : max_part;
+        items += max_workgroups(cases + c);
+        phi += align_up(L.stride * L.cs, kAlign);
+        lat += case_bytes(L);
+    }
+    size_t off = 0;
+    B.off_stage = off;
+    off = align_up(off + 6 * max_nn * sizeof(double), kAlign);
+    B.off_part = off;
+    off = align_up(off + 2 * max_part * sizeof(double), kAlign);
+    B.off_queue = off;
+    off = align_up(off + 2 * sizeof(unsigned), kAlign);
+    B.off_desc = off;
+    off = align_up(off + (size_t)n * kDescBytes, kAlign);
+    B.off_item_case = off;
+    off = align_up(off + items * sizeof(unsigned), kAlign);
+    B.off_first = off;
+    off = align_up(off + (size_t)n * sizeof(unsigned), kAlign);
+    B.off_phi_backup = off;
+    off = align_up(off + phi, kAlign);
+    B.off_cases = off;
+    off += lat;
+    B.total = off;
+    B.max_items = items;
+    return B;
+}
+
+void drop_graphs(lbm_batch *b) {
+    for (int k = 0; k < 2; ++k) {
+        if (b->exec[k]) hipGraphExecDestroy(b->exec[k]);
+        b->exec[k] = nullptr;
+    }
+}
+
+bool tile_supported(int storage, int tx, int ty) {
+    bool ok = false;
+    for (const TileShape &t : kTiles) ok = ok || (t.tx == tx && t.ty == ty);
+    return ok && (storage != LBM_STORE_F64 || tx * ty == 256);
+}
+
+// Work list and step descriptors for the current launch shape.
+template <typename ST>
+int build_batch_tables(lbm_batch *b) {
+    std::vector<lbm::StepArgs<ST>> desc(b->n);
+    std::vector<unsigned> first(b->n), item_case;
+    item_case.reserve(b->max_items);
+    for (int k = 0; k < b->n; ++k) {
+        const int c = b->order[k];
+        lbm_handle *h = b->cases + c;
+        lbm::StepArgs<ST> A;
+        A.pop_in = (const typename ST::T *)h->pop(0);
+        A.pop_out = (typename ST::T *)h->pop(1);
+        A.phi = (typename ST::C *)h->phi();
+        A.rho_ave = h->rho_ave();
+        A.partials = h->partials();
+        A.status = h->status();
+        A.stride = h->L.stride;
+        A.nx = h->p.nx;
+        A.ny = h->p.ny;
+        A.nz = h->p.nz;
+        A.ntx = (h->p.nx + b->tile_x - 1) / b->tile_x;
+        A.nty = (h->p.ny + b->tile_y - 1) / b->tile_y;
+        A.cz = b->chunk_z < h->p.nz ? b->chunk_z : h->p.nz;
+        A.P = make_phys<typename ST::C>(&h->p);
+        desc[c] = A;
+        const unsigned items = (unsigned)(A.ntx * A.nty * ((h->p.nz + A.cz - 1) / A.cz));
+        first[c] = (unsigned)item_case.size();
+        for (unsigned i = 0; i < items; ++i) item_case.push_back((unsigned)c);
+    }
+    if (item_case.size() > b->max_items) return LBM_EINVAL;
+    b->n_items = (unsigned)item_case.size();
+    hipError_t e = hipMemcpyAsync(b->d_desc, desc.data(), desc.size() * sizeof(desc[0]), hipMemcpyHostToDevice,
+                                  b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_item_case, item_case.data(), item_case.size() * sizeof(unsigned),
+                           hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_first_item, first.data(), first.size() * sizeof(unsigned), hipMemcpyHostToDevice,
+                           b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);  // the host vectors go out of scope
+    return hip_status(e);
+}
+
+int default_batch_workgroups(const lbm_batch *b, int tx, int ty) {
+    // Two waves per SIMD fit the step kernel's registers: 8 waves per compute unit.
+    const int per_cu = (8 * 64) / (tx * ty) > 0 ? (8 * 64) / (tx * ty) : 1;
+    return b->cus * per_cu;
+}
+
+template <typename ST, int TX, int TY>
+int launch_batch_t(lbm_batch *b, int parity, int grid) {
+    lbm::BatchQueue Q;
+    Q.item_case = b->d_item_case;
+    Q.first_item = b->d_first_item;
+    Q.n_items = b->n_items;
+    Q.queue = b->d_queue;
+    const lbm::StepArgs<ST> *d = (const lbm::StepArgs<ST> *)b->d_desc;
+    bool buf = true;
+    for (int c = 0; c < b->n; ++c) buf = buf && buffer_path(b->cases[c].L);
+    if (buf)
+        hipLaunchKernelGGL((lbm::k_step_batch<ST, TX, TY, true>), dim3(grid), dim3(TX * TY), 0, b->stream, d, Q,
+                           parity);
+    else
+        hipLaunchKernelGGL((lbm::k_step_batch<ST, TX, TY, false>), dim3(grid), dim3(TX * TY), 0, b->stream, d, Q,
+                           parity);
+    return hip_status(hipGetLastError());
+}
+
+template <typename ST>
+int launch_batch(lbm_batch *b, int parity) {
+    const int tx = b->tile_x, ty = b->tile_y;
+    int grid = b->workgroups > 0 ? b->workgroups : default_batch_workgroups(b, tx, ty);
+    if ((unsigned)grid > b->n_items) grid = (int)b->n_items;
+    if (grid < 1) grid = 1;
+    if (tx == 64 && ty == 4) return launch_batch_t<ST, 64, 4>(b, parity, grid);
+    if (tx == 32 && ty == 8) return launch_batch_t<ST, 32, 8>(b, parity, grid);
+    if constexpr (sizeof(typename ST::C) == 4) {
+        if (tx == 64 && ty == 8) return launch_batch_t<ST, 64, 8>(b, parity, grid);
+        if (tx == 32 && ty == 16) return launch_batch_t<ST, 32, 16>(b, parity, grid);
+        if (tx == 128 && ty == 4) return launch_batch_t<ST, 128, 4>(b, parity, grid);
+    }
+    return LBM_EINVAL;
+}
+
+int batch_launch_one(lbm_batch *b, int parity) {
+    return with_format(b->storage, [&](auto fmt) { return launch_batch<decltype(fmt)>(b, parity); });
+}
+
+int batch_tables(lbm_batch *b) {
+    drop_graphs(b);
+    return with_format(b->storage, [&](auto fmt) { return build_batch_tables<decltype(fmt)>(b); });
+}
+
+// Graph of two steps starting from population copy `from`.
+int batch_graph(lbm_batch *b, int from) {
+    if (b->exec[from]) return LBM_OK;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return LBM_EHIP;
+    int rc = batch_launch_one(b, from);
+    if (!rc) rc = batch_launch_one(b, 1 - from);
+    const hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (rc || e != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return rc ? rc : LBM_EHIP;
+    }
+    const hipError_t ei = hipGraphInstantiate(&b->exec[from], g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    return hip_status(ei);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_batch_arena_bytes(const lbm_params *cases, int ncases) {
+    if (!valid_batch(cases, ncases)) return 0;
+    return make_batch_layout(cases, ncases).total;
+}
+
+int lbm_batch_create(const lbm_params *cases, int ncases, void *dev_arena, size_t arena_bytes, void *hip_stream,
+                     lbm_batch **out) {
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    if (!valid_batch(cases, ncases) || !dev_arena) return LBM_EINVAL;
+    const BatchLayout B = make_batch_layout(cases, ncases);
+    if (arena_bytes < B.total || ((uintptr_t)dev_arena % kAlign) != 0) return LBM_ENOMEM;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        return LBM_EHIP;
+    lbm_batch *b = new lbm_batch();
+    b->n = ncases;
+    b->storage = cases[0].storage;
+    b->stream = (hipStream_t)hip_stream;
+    b->cases = new lbm_handle[ncases]();
+    b->order = new int[ncases];
+    b->cus = cus;
+    char *arena = (char *)dev_arena;
+    b->d_desc = arena + B.off_desc;
+    b->d_item_case = (unsigned *)(arena + B.off_item_case);
+    b->d_first_item = (unsigned *)(arena + B.off_first);
+    b->d_queue = (unsigned *)(arena + B.off_queue);
+    b->d_phi_backup = arena + B.off_phi_backup;
+    b->max_items = B.max_items;
+    b->exec[0] = b->exec[1] = nullptr;
+    size_t off = B.off_cases;
+    size_t largest = 0;
+    for (int c = 0; c < ncases; ++c) {
+        lbm_handle *h = b->cases + c;
+        h->p = cases[c];
+        h->L = make_layout(cases + c);
+        h->stream = b->stream;
+        h->r_pop[0] = arena + off;
+        h->r_pop[1] = h->r_pop[0] + align_up(copy_bytes(h->L), kAlign);
+        h->r_phi = h->r_pop[1] + align_up(copy_bytes(h->L), kAlign);
+        h->r_scal = h->r_phi + align_up(h->L.stride * h->L.cs, kAlign);
+        h->r_stage = (double *)(arena + B.off_stage);
+        h->r_part = (double *)(arena + B.off_part);
+        off += case_bytes(h->L);
+        h->cur = 0;
+        h->initialized = 0;
+        b->order[c] = c;
+        if (h->L.nn > b->cases[largest].L.nn) largest = c;
+    }
+    // Largest lattices first: the long items start early and the small ones fill the tail.
+    std::sort(b->order, b->order + ncases, [&](int a, int c) {
+        return b->cases[a].L.nn != b->cases[c].L.nn ? b->cases[a].L.nn > b->cases[c].L.nn : a < c;
+    });
+    set_default_launch(b->cases + largest);
+    b->tile_x = b->cases[largest].tile_x;
+    b->tile_y = b->cases[largest].tile_y;
+    b->chunk_z = 16;
+    b->workgroups = 0;
+    b->cur = 0;
+    int rc = hip_status(hipMemsetAsync(b->d_queue, 0, 2 * sizeof(unsigned), b->stream));
+    for (int c = 0; c < ncases && !rc; ++c) rc = clear_status(b->cases + c);
+    if (!rc) rc = batch_tables(b);
+    if (rc) {
+        lbm_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+int lbm_batch_init_case(lbm_batch *b, int c, const double *rho, const double *ux, const double *uy,
+                        const double *uz, const double *T) {
+    if (!b || c < 0 || c >= b->n || !rho || !ux || !uy || !uz || !T) return LBM_EINVAL;
+    return init_state(b->cases + c, rho, ux, uy, uz, T, b->cur);
+}
+
+int lbm_batch_step(lbm_batch *b, int n) {
+    if (!b || n < 0) return LBM_EINVAL;
+    for (int c = 0; c < b->n; ++c)
+        if (!b->cases[c].initialized) return LBM_ESTATE;
+    int rc = LBM_OK;
+    if (b->stream) {
+        // pairs of steps as graph replays
+        for (; n >= 2 && !rc; n -= 2) {
+            rc = batch_graph(b, b->cur);
+            if (!rc) rc = hip_status(hipGraphLaunch(b->exec[b->cur], b->stream));
+        }
+    }
+    for (; n > 0 && !rc; --n) {
+        rc = batch_launch_one(b, b->cur);
+        if (!rc) b->cur = 1 - b->cur;
+    }
+    for (int c = 0; c < b->n; ++c) b->cases[c].cur = b->cur;
+    return rc;
+}
+
+int lbm_batch_get_rho_u_T(lbm_batch *b, int c, double *rho, double *ux, double *uy, double *uz, double *T) {
+    if (!b || c < 0 || c >= b->n) return LBM_EINVAL;
+    return lbm_get_rho_u_T(b->cases + c, rho, ux, uy, uz, T);
+}
+
+int lbm_batch_reduce(lbm_batch *b, int c, double *mass, double *energy) {
+    if (!b || c < 0 || c >= b->n) return LBM_EINVAL;
+    return lbm_reduce(b->cases + c, mass, energy);
+}
+
+int lbm_batch_set_launch(lbm_batch *b, int tile_x, int tile_y, int chunk_z, int workgroups) {
+    if (!b || chunk_z < 1 || chunk_z > kMaxChunk || workgroups < 0) return LBM_EINVAL;
+    if (!tile_supported(b->storage, tile_x, tile_y)) return LBM_EINVAL;
+    const int tx = b->tile_x, ty = b->tile_y, cz = b->chunk_z, wg = b->workgroups;
+    b->tile_x = tile_x;
+    b->tile_y = tile_y;
+    b->chunk_z = chunk_z;
+    b->workgroups = workgroups;
+    const int rc = batch_tables(b);
+    if (rc) {
+        b->tile_x = tx;
+        b->tile_y = ty;
+        b->chunk_z = cz;
+        b->workgroups = wg;
+        batch_tables(b);
+    }
+    return rc;
+}
+
+int lbm_batch_get_launch(const lbm_batch *b, int *tile_x, int *tile_y, int *chunk_z, int *workgroups, int *items) {
+    if (!b || !tile_x || !tile_y || !chunk_z || !workgroups || !items) return LBM_EINVAL;
+    *tile_x = b->tile_x;
+    *tile_y = b->tile_y;
+    *chunk_z = b->chunk_z;
+    int grid = b->workgroups > 0 ? b->workgroups : default_batch_workgroups(b, b->tile_x, b->tile_y);
+    if ((unsigned)grid > b->n_items) grid = (int)b->n_items;
+    *workgroups = grid;
+    *items = (int)b->n_items;
+    return LBM_OK;
+}
+
+int lbm_batch_autotune(lbm_batch *b, int steps, double *best_ms) {
+    if (!b || steps < 1 || !best_ms) return LBM_EINVAL;
+    for (int c = 0; c < b->n; ++c)
+        if (!b->cases[c].initialized) return LBM_ESTATE;
+    // keep every phi_s plane: the timed launches update them in place
+    size_t off = 0;
+    for (int c = 0; c < b->n; ++c) {
+        const size_t bytes = b->cases[c].L.nn * b->cases[c].L.cs;
+        if (hipMemcpyAsync(b->d_phi_backup + off, b->cases[c].phi(), bytes, hipMemcpyDeviceToDevice, b->stream) !=
+            hipSuccess)
+            return LBM_EHIP;
+        off += align_up(b->cases[c].L.stride * b->cases[c].L.cs, kAlign);
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return LBM_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return LBM_EHIP;
+    }
+    const int chunks[] = {8, 16, 32};
+    double best = 1e30;
+    int bt[4] = {b->tile_x, b->tile_y, b->chunk_z, b->workgroups};
+    int rc = LBM_OK;
+    for (const TileShape &t : kTiles) {
+        if (!tile_supported(b->storage, t.tx, t.ty)) continue;
+        for (int cz : chunks) {
+            for (int mult = 1; mult <= 2 && !rc; ++mult) {
+                b->tile_x = t.tx;
+                b->tile_y = t.ty;
+                b->chunk_z = cz;
+                b->workgroups = mult * default_batch_workgroups(b, t.tx, t.ty);
+                rc = batch_tables(b);
+                if (!rc) rc = batch_launch_one(b, b->cur);  // warm-up
+                if (!rc) rc = hip_status(hipEventRecord(e0, b->stream));
+                for (int k = 0; k < steps && !rc; ++k) rc = batch_launch_one(b, b->cur);
+                if (!rc) rc = hip_status(hipEventRecord(e1, b->stream));
+                if (!rc) rc = hip_status(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                if (!rc) rc = hip_status(hipEventElapsedTime(&ms, e0, e1));
+                if (!rc && ms / steps < best) {
+                    best = ms / steps;
+                    bt[0] = t.tx;
+                    bt[1] = t.ty;
+                    bt[2] = cz;
+                    bt[3] = b->workgroups;
+                }
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    // restore phi_s and the status words, install the fastest shape
+    off = 0;
+    for (int c = 0; c < b->n && !rc; ++c) {
+        const size_t bytes = b->cases[c].L.nn * b->cases[c].L.cs;
+        rc = hip_status(
+            hipMemcpyAsync(b->cases[c].phi(), b->d_phi_backup + off, bytes, hipMemcpyDeviceToDevice, b->stream));
+        if (!rc) rc = clear_status(b->cases + c);
+        off += align_up(b->cases[c].L.stride * b->cases[c].L.cs, kAlign);
+    }
+    b->tile_x = bt[0];
+    b->tile_y = bt[1];
+    b->chunk_z = bt[2];
+    b->workgroups = bt[3];
+    const int rc2 = batch_tables(b);
+    if (!rc) rc = rc2;
+    if (!rc) rc = hip_status(hipStreamSynchronize(b->stream));
+    *best_ms = best;
+    return rc;
+}
+
+void lbm_batch_destroy(lbm_batch *b) {
+    if (!b) return;
+    drop_graphs(b);
+    delete[] b->cases;
+    delete[] b->order;
+    delete b;
 }
 
 }  // extern "C"

@@ -433,8 +433,11 @@ struct NodePops {
     C e[19], r[7], br, bt;
 };
 
+// One workgroup's share of a time step: the x-y tile and z chunk with index
+// `logical` (x fastest, then y, then the chunk), for the lattice described by
+// A.  `slot` is the workgroup's entry in A.partials (gravity runs only).
 template <typename ST, int TX, int TY, bool WALLS, bool BUF>
-__global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
+__device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, int slot) {
     using E = typename ST::T;  // stored element
     using C = typename ST::C;
     constexpr bool DEV = ST::kDev;
@@ -471,7 +474,6 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
     const unsigned plane = (unsigned)nx * (unsigned)ny;
     const PopIO<E, typename ST::R, BUF> io(A.pop_in, A.pop_out, A.stride);
 
-    const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
     const int itx = logical % A.ntx;
     const int rest = logical / A.ntx;
     const int ity = rest % A.nty;
@@ -901,7 +903,58 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
         if (tid == 0) {
             double acc = 0.0;
             for (int w = 0; w < NT / 64; ++w) acc += s_red[w];
-            A.partials[blockIdx.x] = acc;
+            A.partials[slot] = acc;
+        }
+    }
+}
+
+// One launch per time step: workgroup b takes tile/chunk xcd_logical_block(b).
+template <typename ST, int TX, int TY, bool WALLS, bool BUF>
+__global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
+    step_tile<ST, TX, TY, WALLS, BUF>(A, xcd_logical_block(blockIdx.x, gridDim.x), blockIdx.x);
+}
+
+// Work list of a batch of independent lattices advanced by one launch.
+// Items are (lattice, tile/chunk) pairs, numbered lattice by lattice;
+// item_case[i] is the lattice of item i and first_item[c] the number of the
+// first item of lattice c.  queue[0] hands out items, queue[1] counts
+// workgroups that have finished; the last one resets both, so the next
+// launch (or graph replay) starts from zero without a memset.
+struct BatchQueue {
+    const unsigned *item_case;
+    const unsigned *first_item;
+    unsigned n_items;
+    unsigned *queue;
+};
+
+// Persistent batched step: a fixed grid of workgroups takes items from the
+// shared counter until the list is exhausted, so lattices of uneven size
+// share the GPU without a launch per lattice.  parity = 1 swaps the two
+// population copies of every lattice (steps alternate between them).
+template <typename ST, int TX, int TY, bool BUF>
+__global__ void __launch_bounds__(TX *TY) k_step_batch(const StepArgs<ST> *__restrict__ cases, BatchQueue Q,
+                                                       int parity) {
+    __shared__ unsigned s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(Q.queue, 1u);
+        __syncthreads();
+        const unsigned item = s_item;
+        __syncthreads();  // every thread has read s_item, and the previous item's LDS reads are done
+        if (item >= Q.n_items) break;
+        const unsigned c = Q.item_case[item];
+        StepArgs<ST> A = cases[c];
+        if (parity) {
+            typename ST::T *t = const_cast<typename ST::T *>(A.pop_in);
+            A.pop_in = A.pop_out;
+            A.pop_out = t;
+        }
+        step_tile<ST, TX, TY, false, BUF>(A, (int)(item - Q.first_item[c]), 0);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(Q.queue + 1, 1u) == gridDim.x - 1) {
+            atomicExch(Q.queue, 0u);
+            atomicExch(Q.queue + 1, 0u);
         }
     }
 }

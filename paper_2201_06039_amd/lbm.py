@@ -41,7 +41,10 @@ class LbmParams(ctypes.Structure):
 # Every entry point declared in include/lbm.h.
 EXPORTS = ("lbm_arena_bytes", "lbm_create", "lbm_init_fields", "lbm_step", "lbm_get_rho_u_T", "lbm_reduce",
            "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_set_launch", "lbm_get_launch",
-           "lbm_launches_per_step", "lbm_destroy", "lbm_strerror")
+           "lbm_launches_per_step", "lbm_destroy", "lbm_strerror",
+           "lbm_batch_arena_bytes", "lbm_batch_create", "lbm_batch_init_case", "lbm_batch_step",
+           "lbm_batch_get_rho_u_T", "lbm_batch_reduce", "lbm_batch_set_launch", "lbm_batch_get_launch",
+           "lbm_batch_autotune", "lbm_batch_destroy")
 
 _lib = None
 
@@ -80,8 +83,22 @@ def load_library():
     L.lbm_destroy.restype = None
     L.lbm_strerror.argtypes = [ctypes.c_int]
     L.lbm_strerror.restype = ctypes.c_char_p
+    L.lbm_batch_arena_bytes.argtypes = [P, ctypes.c_int]
+    L.lbm_batch_arena_bytes.restype = ctypes.c_size_t
+    L.lbm_batch_create.argtypes = [P, ctypes.c_int, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.lbm_batch_init_case.argtypes = [vp, ctypes.c_int, dp, dp, dp, dp, dp]
+    L.lbm_batch_step.argtypes = [vp, ctypes.c_int]
+    L.lbm_batch_get_rho_u_T.argtypes = [vp, ctypes.c_int, dp, dp, dp, dp, dp]
+    L.lbm_batch_reduce.argtypes = [vp, ctypes.c_int, dp, dp]
+    L.lbm_batch_set_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.lbm_batch_get_launch.argtypes = [vp, ip, ip, ip, ip, ip]
+    L.lbm_batch_autotune.argtypes = [vp, ctypes.c_int, dp]
+    L.lbm_batch_destroy.argtypes = [vp]
+    L.lbm_batch_destroy.restype = None
     for name in ("lbm_create", "lbm_init_fields", "lbm_step", "lbm_get_rho_u_T", "lbm_reduce", "lbm_get_state",
-                 "lbm_set_state", "lbm_set_launch", "lbm_get_launch", "lbm_launches_per_step"):
+                 "lbm_set_state", "lbm_set_launch", "lbm_get_launch", "lbm_launches_per_step",
+                 "lbm_batch_create", "lbm_batch_init_case", "lbm_batch_step", "lbm_batch_get_rho_u_T",
+                 "lbm_batch_reduce", "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_autotune"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -118,6 +135,17 @@ def make_params(params: dict, storage="f32") -> LbmParams:
 
 def arena_bytes(params: dict, storage="f32") -> int:
     return load_library().lbm_arena_bytes(ctypes.byref(make_params(params, storage)))
+
+
+def _params_array(cases, storage):
+    arr = (LbmParams * len(cases))()
+    for i, c in enumerate(cases):
+        arr[i] = make_params(c, storage)
+    return arr
+
+
+def batch_arena_bytes(cases, storage="f16") -> int:
+    return load_library().lbm_batch_arena_bytes(_params_array(cases, storage), len(cases))
 
 
 def _dp(a):
@@ -200,3 +228,85 @@ class Lattice:
 
     def launches_per_step(self):
         return self.lib.lbm_launches_per_step(self._h)
+
+
+class Batch:
+    """Many independent lattices advanced by one launch per time step.
+
+    `cases` is a list of parameter dicts (periodic, no gravity, one storage
+    format for all).  The batch runs on a stream of its own (default
+    priority) so that lbm_batch_step can replay captured graphs; readouts
+    synchronise it."""
+
+    def __init__(self, cases, storage="f16", device="cuda", stream=None):
+        import torch
+        self._torch = torch
+        self.lib = load_library()
+        self._params = _params_array(cases, storage)
+        self.n = len(cases)
+        self.shapes = [(p.nz, p.ny, p.nx) for p in self._params]
+        nbytes = self.lib.lbm_batch_arena_bytes(self._params, self.n)
+        if nbytes == 0:
+            raise LbmError("lbm_batch_arena_bytes", EINVAL)
+        self.arena = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.arena.device)
+        # the arena was allocated on torch's current stream; order the batch's stream after it
+        self.stream.wait_stream(torch.cuda.current_stream(self.arena.device))
+        h = ctypes.c_void_p()
+        rc = self.lib.lbm_batch_create(self._params, self.n, ctypes.c_void_p(self.arena.data_ptr()), nbytes,
+                                       ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc != OK:
+            raise LbmError("lbm_batch_create", rc)
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            # the arena goes back to torch's allocator: let the batch's stream finish with it first
+            self.stream.synchronize()
+            self.lib.lbm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, call, rc):
+        if rc != OK:
+            raise LbmError(call, rc)
+
+    def init_case(self, c, rho, ux, uy, uz, T):
+        nn = int(np.prod(self.shapes[c]))
+        arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1)) for a in (rho, ux, uy, uz, T)]
+        for a in arrs:
+            if a.size != nn:
+                raise ValueError(f"case {c}: expected {nn} values, got {a.size}")
+        self._check("lbm_batch_init_case", self.lib.lbm_batch_init_case(self._h, int(c), *[_dp(a) for a in arrs]))
+
+    def step(self, n=1):
+        self._check("lbm_batch_step", self.lib.lbm_batch_step(self._h, int(n)))
+
+    def rho_u_T(self, c):
+        nn = int(np.prod(self.shapes[c]))
+        out = [np.empty(nn) for _ in range(5)]
+        self._check("lbm_batch_get_rho_u_T", self.lib.lbm_batch_get_rho_u_T(self._h, int(c), *[_dp(a) for a in out]))
+        return tuple(a.reshape(self.shapes[c]) for a in out)
+
+    def reduce(self, c):
+        m, e = ctypes.c_double(), ctypes.c_double()
+        self._check("lbm_batch_reduce", self.lib.lbm_batch_reduce(self._h, int(c), ctypes.byref(m), ctypes.byref(e)))
+        return m.value, e.value
+
+    def set_launch(self, tile_x, tile_y, chunk_z, workgroups=0):
+        self._check("lbm_batch_set_launch", self.lib.lbm_batch_set_launch(self._h, tile_x, tile_y, chunk_z,
+                                                                          workgroups))
+
+    def launch(self):
+        v = [ctypes.c_int() for _ in range(5)]
+        self._check("lbm_batch_get_launch", self.lib.lbm_batch_get_launch(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(tile_x=v[0].value, tile_y=v[1].value, chunk_z=v[2].value, workgroups=v[3].value,
+                    items=v[4].value)
+
+    def autotune(self, steps=10):
+        ms = ctypes.c_double()
+        self._check("lbm_batch_autotune", self.lib.lbm_batch_autotune(self._h, int(steps), ctypes.byref(ms)))
+        return ms.value
+

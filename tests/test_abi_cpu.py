@@ -102,3 +102,28 @@ def test_create_rejects_bad_arguments_before_any_device_call(lib):
 def test_strerror(lib):
     for code in (0, -1, -2, -3, -4, -5, 17):
         assert isinstance(lib.lbm_strerror(code), bytes)
+
+
+def test_batch_validation(lib):
+    """A batch takes periodic lattices without gravity, all in one storage
+    format; its arena holds every lattice's own regions."""
+    from paper_2201_06039_amd import lbm, workloads as W
+    a = dict(W.load("static_droplet_32")["params"])
+    b = dict(a, nx=24, ny=20, nz=18)
+    c = dict(W.load("d2_law_48")["params"])
+    good = lbm.batch_arena_bytes([a, b, c], "f16")
+    assert good > lbm.arena_bytes(a, "f16") + lbm.arena_bytes(b, "f16") - 2 * 6 * 8 * 32 ** 3
+    assert lbm.batch_arena_bytes([a], "f32") > 0
+    assert lbm.batch_arena_bytes([], "f16") == 0
+    walls = dict(W.load("pool_boiling_32x32x48")["params"], grav=[0.0, 0.0, 0.0])
+    gravity = dict(a, grav=[0.0, 0.0, -1e-5])
+    for bad in ([a, walls], [a, gravity], [a, dict(a, tau_v=0.4)]):
+        assert lbm.batch_arena_bytes(bad, "f16") == 0
+    p = lbm._params_array([a, b], "f16")
+    p[1].storage = lbm.STORE_F32
+    assert lib.lbm_batch_arena_bytes(p, 2) == 0
+    h = ctypes.c_void_p()
+    assert lib.lbm_batch_create(p, 2, ctypes.c_void_p(256), 1 << 40, None, ctypes.byref(h)) == lbm.EINVAL
+    assert lib.lbm_batch_step(None, 1) == lbm.EINVAL
+    lib.lbm_batch_destroy(None)
+

@@ -1,0 +1,154 @@
+"""Batches of independent lattices (one persistent launch per step, graph
+replays of two steps): every lattice of a batch must equal its stand-alone
+run bit for bit, through graph replays, direct launches, the autotuner and
+the null stream; and an FP64 batch must match the oracle."""
+import copy
+
+import numpy as np
+import pytest
+
+from parity_util import errors, run_oracle, workload
+from paper_2201_06039_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def small_cases():
+    """Uneven lattices: cubes and ragged boxes, static and evaporating
+    droplets, one with the reservoir boundary."""
+    out = []
+    evap = W.load("evaporation_128")
+    for (nx, ny, nz), R, hot, shell in [((24, 24, 24), 6.0, False, False),
+                                        ((30, 26, 22), 6.5, True, False),
+                                        ((40, 40, 40), 9.0, True, False),
+                                        ((17, 33, 28), 5.0, False, False),
+                                        ((26, 22, 20), 6.0, True, True),
+                                        ((48, 48, 48), 11.0, False, False)]:
+        w = copy.deepcopy(evap)
+        w["params"].update(nx=nx, ny=ny, nz=nz)
+        w["init"].update(radius=R, center=[nx / 2 - 0.3, ny / 2 + 0.2, nz / 2 - 0.1], seed=len(out))
+        if not hot:
+            w["init"]["T_v"] = w["init"]["T_l"]
+        if shell:
+            w["params"].update(bc_T_shell=1, T_shell=w["init"]["T_v"])
+        out.append(w)
+    return out
+
+
+def solo(w, storage, schedule):
+    from paper_2201_06039_amd import lbm
+    lat = lbm.Lattice(w["params"], storage=storage, device="cuda:0")
+    lat.init_fields(*W.fields(w))
+    outs = []
+    for n in schedule:
+        lat.step(n)
+        outs.append(lat.rho_u_T())
+    lat.close()
+    return outs
+
+
+def make_batch(cases, storage, stream=None):
+    from paper_2201_06039_amd import lbm
+    b = lbm.Batch([w["params"] for w in cases], storage=storage, device="cuda:0", stream=stream)
+    for c, w in enumerate(cases):
+        b.init_case(c, *W.fields(w))
+    return b
+
+
+SCHEDULE = [1, 4, 3, 2]  # a direct launch, two graph replays, a replay and a direct launch, one replay
+
+
+@pytest.mark.parametrize("storage", ["f16", "f32"])
+def test_batch_equals_solo_runs(storage):
+    cases = small_cases()
+    b = make_batch(cases, storage)
+    _say(f"batch {storage}: launch {b.launch()}")
+    ref = [solo(w, storage, SCHEDULE) for w in cases]
+    for k, n in enumerate(SCHEDULE):
+        b.step(n)
+        for c in range(len(cases)):
+            got = b.rho_u_T(c)
+            for x, y in zip(got, ref[c][k]):
+                assert np.array_equal(x, y), (storage, k, c)
+        _say(f"  after {sum(SCHEDULE[:k + 1])} steps: all {len(cases)} lattices bitwise equal to their solo runs")
+    b.close()
+
+
+@pytest.mark.parametrize("launch", [(32, 8, 8, 0), (64, 8, 32, 7), (128, 4, 4, 1), (32, 16, 16, 1000)])
+def test_batch_launch_shapes(launch):
+    """Tile, chunk and persistent-grid size (one workgroup included) change
+    nothing in the results."""
+    cases = small_cases()[:4]
+    b = make_batch(cases, "f16")
+    b.set_launch(*launch)
+    _say(f"batch launch {b.launch()}")
+    ref = [solo(w, "f16", [5]) for w in cases]
+    b.step(5)
+    for c in range(len(cases)):
+        for x, y in zip(b.rho_u_T(c), ref[c][0]):
+            assert np.array_equal(x, y), (launch, c)
+    b.close()
+
+
+def test_autotune_leaves_the_state_unchanged():
+    cases = small_cases()
+    b = make_batch(cases, "f16")
+    b.step(3)
+    ms = b.autotune(steps=2)
+    _say(f"autotune: {ms:.4f} ms/step with {b.launch()}")
+    assert ms > 0
+    b.step(4)
+    ref = [solo(w, "f16", [7]) for w in cases]
+    for c in range(len(cases)):
+        for x, y in zip(b.rho_u_T(c), ref[c][0]):
+            assert np.array_equal(x, y), c
+    b.close()
+
+
+def test_batch_on_the_null_stream():
+    """Without a stream of its own the batch launches directly (no graphs)."""
+    import torch
+    cases = small_cases()[:3]
+    b = make_batch(cases, "f16", stream=torch.cuda.default_stream())
+    ref = [solo(w, "f16", [4]) for w in cases]
+    b.step(4)
+    for c in range(len(cases)):
+        for x, y in zip(b.rho_u_T(c), ref[c][0]):
+            assert np.array_equal(x, y), c
+    b.close()
+
+
+def test_fp64_batch_against_oracle():
+    cases = [workload("static_droplet_32", nx=20, ny=18, nz=16, radius=5.0),
+             workload("evaporation_128", nx=24, ny=24, nz=24, radius=6.0),
+             workload("d2_law_48", nx=22, ny=20, nz=18, radius=5.0)]
+    b = make_batch(cases, "f64")
+    b.step(30)
+    for c, w in enumerate(cases):
+        e = errors(b.rho_u_T(c), run_oracle(w, 30))
+        _say(f"  case {c}: {e}")
+        assert e["rho"] <= 1e-12 and e["T"] <= 1e-12 and e["u"] <= 1e-12, (c, e)
+    b.close()
+
+
+def test_batch_reduce_and_readout_errors():
+    from paper_2201_06039_amd import lbm
+    cases = small_cases()[:2]
+    b = lbm.Batch([w["params"] for w in cases], storage="f16", device="cuda:0")
+    with pytest.raises(lbm.LbmError) as ei:
+        b.step(1)  # nothing initialised yet
+    assert ei.value.status == lbm.ESTATE
+    for c, w in enumerate(cases):
+        b.init_case(c, *W.fields(w))
+    m0 = [b.reduce(c)[0] for c in range(2)]
+    b.step(10)
+    m1 = [b.reduce(c)[0] for c in range(2)]
+    for a, z in zip(m0, m1):
+        assert abs(z - a) / a < 1e-5
+    assert b.lib.lbm_batch_get_rho_u_T(b._h, 5, None, None, None, None, None) == lbm.EINVAL
+    assert b.lib.lbm_batch_set_launch(b._h, 48, 8, 16, 0) == lbm.EINVAL
+    b.close()
