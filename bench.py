@@ -2,7 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                     [--storage f16|f32|f64|bf16|f32dev] [--compare f32|none]
-                    [--tile TXxTY] [--chunk CZ] [--no-precision] [--no-cpu-baseline]
+                    [--tile TXxTY] [--chunk CZ] [--no-precision] [--no-batch] [--no-cpu-baseline]
 
 One step = one fused time step of the whole grid (both lattices, streaming and
 boundary rules) on synthetic seeded input already resident in HBM.  Prints one
@@ -10,8 +10,9 @@ JSON line: MLUPS (million lattice-node updates per second) of the chosen
 population storage (FP16 deviations by default), the HBM roofline of the step
 kernel, the same step with FP32 storage for comparison, the errors of the
 storage format against the FP64 oracle's reference values (coexistence
-densities, Laplace jump, D^2 slope), and the FP64 oracle timed on the host as
-a CPU baseline.
+densities, Laplace jump, D^2 slope), the batched step over 256 independent
+lattices of uneven size (aggregate MLUPS after autotuning), and the FP64
+oracle timed on the host as a CPU baseline.
 """
 import argparse
 import hashlib
@@ -130,6 +131,38 @@ def precision_errors(storage):
     return out
 
 
+def batch_run(storage, steps, warmup, name="batch_256"):
+    """The batched step over the lattices of workload `name`: autotune the
+    launch on the initial state, then time `steps` steps (graph replays)."""
+    import torch
+    from paper_2201_06039_amd import lbm, workloads as W
+    wb = W.load(name)
+    cases = wb["cases"]
+    b = lbm.Batch([c["params"] for c in cases], storage=storage, device="cuda:0")
+    for i, c in enumerate(cases):
+        b.init_case(i, *W.fields(c))
+    tuned_ms = b.autotune(steps=5)
+    launch = b.launch()
+    b.step(warmup)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(b.stream)
+    b.step(steps)
+    end.record(b.stream)
+    end.synchronize()
+    ms = start.elapsed_time(end) / steps
+    for i in range(len(cases)):
+        b.reduce(i)  # raises if any lattice went unstable
+    b.close()
+    nodes = wb["nodes"]
+    tx, ty = launch["tile_x"], launch["tile_y"]
+    slots = sum(-(-c["params"]["nx"] // tx) * tx * -(-c["params"]["ny"] // ty) * ty * c["params"]["nz"] for c in cases)
+    return {"workload": name, "cases": len(cases), "nodes": nodes, "storage": storage,
+            "value": round(nodes / ms / 1e3, 2), "unit": "MLUPS", "ms_per_step": round(ms, 5), "steps": steps,
+            "roofline_frac": round(BYTES_PER_LUP[storage] * nodes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "launch": launch, "autotune_ms_per_step": round(tuned_ms, 5),
+            "thread_slot_efficiency": round(nodes / slots, 4), "graph": True}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +175,8 @@ def main():
     ap.add_argument("--tile", default=None, help="TXxTY, e.g. 64x4")
     ap.add_argument("--chunk", type=int, default=None)
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="only run 20 plain device-to-device copies of MB megabytes (to calibrate the "
@@ -226,6 +261,9 @@ def main():
         print(f"# precision of {args.storage}: {errs}", file=sys.stderr, flush=True)
         out["precision"] = {"storage": args.storage, "reference": "FP64 oracle", "bound": PRECISION_BOUND,
                             "relative_errors": errs, "within_bound": max(errs.values()) <= PRECISION_BOUND}
+    if not args.no_batch:
+        out["batch"] = batch_run(args.storage if args.storage != "f64" else "f32", args.batch_steps, 10)
+        print(f"# batch: {out['batch']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, fields)
     print(json.dumps(out), flush=True)

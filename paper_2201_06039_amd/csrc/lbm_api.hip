@@ -641,6 +641,7 @@ struct lbm_batch {
     // launch
     int tile_x, tile_y, chunk_z, workgroups;
     unsigned n_items;
+    unsigned bin_start[lbm::kXcds + 1];  // item ranges of the XCDs
     int cur;               // population copy holding the state of every lattice
     hipGraphExec_t exec[2];  // two steps starting from copy 0 / copy 1
 };
@@ -688,7 +689,7 @@ BatchLayout make_batch_layout(const lbm_params *cases, int n) {
     B.off_part = off;
     off = align_up(off + 2 * max_part * sizeof(double), kAlign);
     B.off_queue = off;
-    off = align_up(off + 2 * sizeof(unsigned), kAlign);
+    off = align_up(off + (lbm::kXcds + 1) * sizeof(unsigned), kAlign);
     B.off_desc = off;
     off = align_up(off + (size_t)n * kDescBytes, kAlign);
     B.off_item_case = off;
@@ -717,14 +718,34 @@ bool tile_supported(int storage, int tx, int ty) {
     return ok && (storage != LBM_STORE_F64 || tx * ty == 256);
 }
 
-// Work list and step descriptors for the current launch shape.
+// Work list and step descriptors for the current launch shape.  Lattices
+// are dealt to the XCDs largest first, each to the XCD with the least work so
+// far (nodes, idle tile slots included); every XCD's items are contiguous.
 template <typename ST>
 int build_batch_tables(lbm_batch *b) {
     std::vector<lbm::StepArgs<ST>> desc(b->n);
     std::vector<unsigned> first(b->n), item_case;
+    std::vector<int> bin_of(b->n);
     item_case.reserve(b->max_items);
+    {
+        double load[lbm::kXcds] = {0};
+        for (int k = 0; k < b->n; ++k) {
+            const int c = b->order[k];
+            const lbm_params &p = b->cases[c].p;
+            const double slots = (double)((p.nx + b->tile_x - 1) / b->tile_x * b->tile_x) *
+                                 ((p.ny + b->tile_y - 1) / b->tile_y * b->tile_y) * p.nz;
+            int best = 0;
+            for (int x = 1; x < lbm::kXcds; ++x)
+                if (load[x] < load[best]) best = x;
+            load[best] += slots;
+            bin_of[c] = best;
+        }
+    }
+    for (int x = 0; x <= lbm::kXcds; ++x) b->bin_start[x] = 0;
+    for (int pass = 0; pass < lbm::kXcds; ++pass)
     for (int k = 0; k < b->n; ++k) {
         const int c = b->order[k];
+        if (bin_of[c] != pass) continue;
         lbm_handle *h = b->cases + c;
         lbm::StepArgs<ST> A;
         A.pop_in = (const typename ST::T *)h->pop(0);
@@ -745,7 +766,10 @@ int build_batch_tables(lbm_batch *b) {
         const unsigned items = (unsigned)(A.ntx * A.nty * ((h->p.nz + A.cz - 1) / A.cz));
         first[c] = (unsigned)item_case.size();
         for (unsigned i = 0; i < items; ++i) item_case.push_back((unsigned)c);
+        b->bin_start[pass + 1] = (unsigned)item_case.size();
     }
+    for (int x = 1; x <= lbm::kXcds; ++x)
+        if (b->bin_start[x] < b->bin_start[x - 1]) b->bin_start[x] = b->bin_start[x - 1];
     if (item_case.size() > b->max_items) return LBM_EINVAL;
     b->n_items = (unsigned)item_case.size();
     hipError_t e = hipMemcpyAsync(b->d_desc, desc.data(), desc.size() * sizeof(desc[0]), hipMemcpyHostToDevice,
@@ -771,8 +795,8 @@ int launch_batch_t(lbm_batch *b, int parity, int grid) {
     lbm::BatchQueue Q;
     Q.item_case = b->d_item_case;
     Q.first_item = b->d_first_item;
-    Q.n_items = b->n_items;
     Q.queue = b->d_queue;
+    for (int x = 0; x <= lbm::kXcds; ++x) Q.bin_start[x] = b->bin_start[x];
     const lbm::StepArgs<ST> *d = (const lbm::StepArgs<ST> *)b->d_desc;
     bool buf = true;
     for (int c = 0; c < b->n; ++c) buf = buf && buffer_path(b->cases[c].L);
@@ -891,7 +915,7 @@ int lbm_batch_create(const lbm_params *cases, int ncases, void *dev_arena, size_
     b->chunk_z = 16;
     b->workgroups = 0;
     b->cur = 0;
-    int rc = hip_status(hipMemsetAsync(b->d_queue, 0, 2 * sizeof(unsigned), b->stream));
+    int rc = hip_status(hipMemsetAsync(b->d_queue, 0, (lbm::kXcds + 1) * sizeof(unsigned), b->stream));
     for (int c = 0; c < ncases && !rc; ++c) rc = clear_status(b->cases + c);
     if (!rc) rc = batch_tables(b);
     if (rc) {

@@ -915,46 +915,57 @@ __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
 }
 
 // Work list of a batch of independent lattices advanced by one launch.
-// Items are (lattice, tile/chunk) pairs, numbered lattice by lattice;
-// item_case[i] is the lattice of item i and first_item[c] the number of the
-// first item of lattice c.  queue[0] hands out items, queue[1] counts
-// workgroups that have finished; the last one resets both, so the next
-// launch (or graph replay) starts from zero without a memset.
+// Items are (lattice, tile/chunk) pairs.  The lattices are dealt to the 8 XCDs
+// (balanced by work) and the items of the lattices of XCD x are the range
+// [bin_start[x], bin_start[x+1]); item_case[i] is the lattice of item i and
+// first_item[c] the number of the first item of lattice c.  Counter x of
+// `queue` hands out the items of range x; queue[8] counts workgroups that have
+// finished, and the last one resets all nine, so the next launch (or graph
+// replay) starts from zero without a memset.
+constexpr int kXcds = 8;
 struct BatchQueue {
     const unsigned *item_case;
     const unsigned *first_item;
-    unsigned n_items;
     unsigned *queue;
+    unsigned bin_start[kXcds + 1];
 };
 
 // Persistent batched step: a fixed grid of workgroups takes items from the
-// shared counter until the list is exhausted, so lattices of uneven size
-// share the GPU without a launch per lattice.  parity = 1 swaps the two
-// population copies of every lattice (steps alternate between them).
+// counters until every range is exhausted, so lattices of uneven size share
+// the GPU without a launch per lattice.  Workgroup b runs on XCD b mod 8
+// (round-robin dispatch) and drains that XCD's range first, so neighbouring
+// tiles of a lattice -- which share halo rows and the cache lines at tile
+// edges -- meet in one L2; it then helps with the other ranges.  parity = 1
+// swaps the two population copies of every lattice.
 template <typename ST, int TX, int TY, bool BUF>
 __global__ void __launch_bounds__(TX *TY) k_step_batch(const StepArgs<ST> *__restrict__ cases, BatchQueue Q,
                                                        int parity) {
     __shared__ unsigned s_item;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(Q.queue, 1u);
-        __syncthreads();
-        const unsigned item = s_item;
-        __syncthreads();  // every thread has read s_item, and the previous item's LDS reads are done
-        if (item >= Q.n_items) break;
-        const unsigned c = Q.item_case[item];
-        StepArgs<ST> A = cases[c];
-        if (parity) {
-            typename ST::T *t = const_cast<typename ST::T *>(A.pop_in);
-            A.pop_in = A.pop_out;
-            A.pop_out = t;
+    const int home = (int)(blockIdx.x % kXcds);
+    for (int k = 0; k < kXcds; ++k) {
+        const int bin = (home + k) % kXcds;
+        const unsigned begin = Q.bin_start[bin], count = Q.bin_start[bin + 1] - begin;
+        for (;;) {
+            if (threadIdx.x == 0) s_item = atomicAdd(Q.queue + bin, 1u);
+            __syncthreads();
+            const unsigned local = s_item;
+            __syncthreads();  // every thread has read s_item, and the previous item's LDS reads are done
+            if (local >= count) break;
+            const unsigned item = begin + local;
+            const unsigned c = Q.item_case[item];
+            StepArgs<ST> A = cases[c];
+            if (parity) {
+                typename ST::T *t = const_cast<typename ST::T *>(A.pop_in);
+                A.pop_in = A.pop_out;
+                A.pop_out = t;
+            }
+            step_tile<ST, TX, TY, false, BUF>(A, (int)(item - Q.first_item[c]), 0);
         }
-        step_tile<ST, TX, TY, false, BUF>(A, (int)(item - Q.first_item[c]), 0);
     }
     if (threadIdx.x == 0) {
         __threadfence();
-        if (atomicAdd(Q.queue + 1, 1u) == gridDim.x - 1) {
-            atomicExch(Q.queue, 0u);
-            atomicExch(Q.queue + 1, 0u);
+        if (atomicAdd(Q.queue + kXcds, 1u) == gridDim.x - 1) {
+            for (int k = 0; k <= kXcds; ++k) atomicExch(Q.queue + k, 0u);
         }
     }
 }

@@ -152,3 +152,30 @@ def test_batch_reduce_and_readout_errors():
     assert b.lib.lbm_batch_get_rho_u_T(b._h, 5, None, None, None, None, None) == lbm.EINVAL
     assert b.lib.lbm_batch_set_launch(b._h, 48, 8, 16, 0) == lbm.EINVAL
     b.close()
+
+
+def test_full_batch_256_sampled_cases_equal_solo_runs():
+    """The benchmark's batch (256 lattices, 74.5 M nodes, FP16) in its
+    autotuned launch: after 20 steps (graph replays) the smallest, the largest
+    and two more lattices equal their stand-alone runs bit for bit, and no
+    lattice is unstable."""
+    from paper_2201_06039_amd import lbm
+    wb = W.load("batch_256")
+    cases = wb["cases"]
+    b = lbm.Batch([c["params"] for c in cases], storage="f16", device="cuda:0")
+    for i, c in enumerate(cases):
+        b.init_case(i, *W.fields(c))
+    ms = b.autotune(steps=3)
+    _say(f"batch_256: autotuned {b.launch()} at {ms:.3f} ms/step")
+    b.step(20)
+    sizes = [c["params"]["nx"] for c in cases]
+    picks = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 17, 200})
+    for i in range(len(cases)):
+        b.reduce(i)  # raises on an unstable lattice
+    for i in picks:
+        tile = b.launch()
+        ref = solo(cases[i], "f16", [20])[0]
+        for x, y in zip(b.rho_u_T(i), ref):
+            assert np.array_equal(x, y), (i, tile)
+        _say(f"  lattice {i} (L = {sizes[i]}) bitwise equal to its solo run")
+    b.close()
