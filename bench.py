@@ -131,9 +131,10 @@ def precision_errors(storage):
     return out
 
 
-def batch_run(storage, steps, warmup, name="batch_256"):
+def batch_run(storage, steps, warmup, name="batch_256", launch=None):
     """The batched step over the lattices of workload `name`: autotune the
-    launch on the initial state, then time `steps` steps (graph replays)."""
+    launch on the initial state (or take `launch` = (tile_x, tile_y, chunk_z,
+    workgroups)), then time `steps` steps (graph replays)."""
     import torch
     from paper_2201_06039_amd import lbm, workloads as W
     wb = W.load(name)
@@ -141,7 +142,11 @@ def batch_run(storage, steps, warmup, name="batch_256"):
     b = lbm.Batch([c["params"] for c in cases], storage=storage, device="cuda:0")
     for i, c in enumerate(cases):
         b.init_case(i, *W.fields(c))
-    tuned_ms = b.autotune(steps=5)
+    if launch:
+        b.set_launch(*launch)
+        tuned_ms = None
+    else:
+        tuned_ms = round(b.autotune(steps=5), 5)
     launch = b.launch()
     b.step(warmup)
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -159,7 +164,7 @@ def batch_run(storage, steps, warmup, name="batch_256"):
     return {"workload": name, "cases": len(cases), "nodes": nodes, "storage": storage,
             "value": round(nodes / ms / 1e3, 2), "unit": "MLUPS", "ms_per_step": round(ms, 5), "steps": steps,
             "roofline_frac": round(BYTES_PER_LUP[storage] * nodes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-            "launch": launch, "autotune_ms_per_step": round(tuned_ms, 5),
+            "launch": launch, "autotune_ms_per_step": tuned_ms,
             "thread_slot_efficiency": round(nodes / slots, 4), "graph": True}
 
 
@@ -176,7 +181,10 @@ def main():
     ap.add_argument("--chunk", type=int, default=None)
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-only", action="store_true", help="run only the batched leg and print its JSON")
     ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--batch-launch", default=None, metavar="TXxTYxCZxWG",
+                    help="fixed batch launch (tile, chunk, workgroups) instead of the autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="only run 20 plain device-to-device copies of MB megabytes (to calibrate the "
@@ -208,6 +216,12 @@ def main():
         return
 
     from paper_2201_06039_amd import lbm, workloads as W
+
+    if args.batch_only:
+        bl = tuple(int(v) for v in args.batch_launch.split("x")) if args.batch_launch else None
+        out = batch_run(args.storage, args.batch_steps, args.warmup, launch=bl)
+        print(json.dumps(out), flush=True)
+        return
 
     w = W.load(args.workload)
     fields = W.fields(w)
@@ -262,7 +276,8 @@ def main():
         out["precision"] = {"storage": args.storage, "reference": "FP64 oracle", "bound": PRECISION_BOUND,
                             "relative_errors": errs, "within_bound": max(errs.values()) <= PRECISION_BOUND}
     if not args.no_batch:
-        out["batch"] = batch_run(args.storage if args.storage != "f64" else "f32", args.batch_steps, 10)
+        bl = tuple(int(v) for v in args.batch_launch.split("x")) if args.batch_launch else None
+        out["batch"] = batch_run(args.storage if args.storage != "f64" else "f32", args.batch_steps, 10, launch=bl)
         print(f"# batch: {out['batch']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, fields)

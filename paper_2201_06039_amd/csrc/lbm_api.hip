@@ -82,11 +82,26 @@ size_t max_workgroups(const lbm_params *p) {
 
 size_t copy_bytes(const Layout &L) { return L.stride * (26 * L.es + (L.planes - 26) * L.rs); }
 
-// Byte offset of plane a (0..25 populations, 26..27 references) in a copy.
-size_t plane_offset(const Layout &L, size_t a) {
-    return a < 26 ? a * L.stride * L.es : 26 * L.stride * L.es + (a - 26) * L.stride * L.rs;
+// Physical planes of a copy, as stored: the plain layout has the 26
+// population planes and (deviation formats) the two reference planes; the
+// paired layout of 16-bit formats has 13 planes of population pairs, then
+// one pair plane of 16-bit references or two planes of 32-bit ones.
+bool paired(const Layout &L) { return L.es == 2; }
+size_t phys_planes(const Layout &L) {
+    if (!paired(L)) return L.planes;
+    return 13 + (L.rs == 2 ? 1 : 2);
 }
-size_t plane_bytes(const Layout &L, size_t a) { return L.nn * (a < 26 ? L.es : L.rs); }
+size_t plane_offset(const Layout &L, size_t k) {
+    if (paired(L)) {
+        if (k < 13 || L.rs == 2) return k * L.stride * 4;
+        return 26 * L.stride * L.es + (k - 13) * L.stride * L.rs;
+    }
+    return k < 26 ? k * L.stride * L.es : 26 * L.stride * L.es + (k - 26) * L.stride * L.rs;
+}
+size_t plane_bytes(const Layout &L, size_t k) {
+    if (paired(L)) return L.nn * 4;
+    return L.nn * (k < 26 ? L.es : L.rs);
+}
 
 Layout make_layout(const lbm_params *p) {
     Layout L;
@@ -168,7 +183,7 @@ struct StateHeader {
     int32_t version, nx, ny, nz, storage, planes;
     uint64_t nn, es, cs;
 };
-constexpr int32_t kStateVersion = 2;
+constexpr int32_t kStateVersion = 3;
 
 // Calls fn with a value of the storage-format type of `storage`.
 template <typename Fn>
@@ -503,7 +518,7 @@ size_t lbm_state_bytes(const lbm_handle *h) {
     if (!h) return 0;
     const size_t nn = h->L.nn;
     size_t planes = 0;
-    for (size_t a = 0; a < h->L.planes; ++a) planes += plane_bytes(h->L, a);
+    for (size_t a = 0; a < phys_planes(h->L); ++a) planes += plane_bytes(h->L, a);
     return sizeof(StateHeader) + planes + nn * h->L.cs + sizeof(double);
 }
 
@@ -514,7 +529,7 @@ int lbm_get_state(lbm_handle *h, void *host_buf, size_t bytes) {
     memset(&hd, 0, sizeof(hd));
     memcpy(hd.magic, "LBMSTAT1", 8);
     hd.version = kStateVersion;
-    hd.planes = (int32_t)h->L.planes;
+    hd.planes = (int32_t)phys_planes(h->L);
     hd.nx = h->p.nx;
     hd.ny = h->p.ny;
     hd.nz = h->p.nz;
@@ -525,7 +540,7 @@ int lbm_get_state(lbm_handle *h, void *host_buf, size_t bytes) {
     char *out = (char *)host_buf;
     memcpy(out, &hd, sizeof(hd));
     out += sizeof(hd);
-    for (size_t a = 0; a < h->L.planes; ++a) {
+    for (size_t a = 0; a < phys_planes(h->L); ++a) {
         const size_t bytes = plane_bytes(h->L, a);
         if (hipMemcpyAsync(out, (char *)h->pop(h->cur) + plane_offset(h->L, a), bytes, hipMemcpyDeviceToHost,
                            h->stream) != hipSuccess)
@@ -552,12 +567,12 @@ int lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes) {
     StateHeader hd;
     memcpy(&hd, host_buf, sizeof(hd));
     if (memcmp(hd.magic, "LBMSTAT1", 8) != 0 || hd.version != kStateVersion || hd.nx != h->p.nx ||
-        hd.ny != h->p.ny || hd.nz != h->p.nz || hd.storage != h->p.storage || hd.planes != (int32_t)h->L.planes ||
+        hd.ny != h->p.ny || hd.nz != h->p.nz || hd.storage != h->p.storage || hd.planes != (int32_t)phys_planes(h->L) ||
         hd.nn != h->L.nn || hd.es != h->L.es || hd.cs != h->L.cs)
         return LBM_EINVAL;
     const char *in = (const char *)host_buf + sizeof(hd);
     h->cur = 0;
-    for (size_t a = 0; a < h->L.planes; ++a) {
+    for (size_t a = 0; a < phys_planes(h->L); ++a) {
         const size_t bytes = plane_bytes(h->L, a);
         if (hipMemcpyAsync((char *)h->pop(0) + plane_offset(h->L, a), in, bytes, hipMemcpyHostToDevice, h->stream) !=
             hipSuccess)

@@ -338,23 +338,40 @@ constexpr int kBufferFlags = 0x00020000;  // raw dword buffer; the record count 
 constexpr int kSplitPlane = 14;           // population planes [0,14) and [14,26) + references: two resources
 constexpr int kPopPlanes = 26;
 
-// Access to the planes of the two ping-pong copies.  A copy holds 26
-// population planes of T, `stride` elements apart, then (deviation formats)
-// the rho_r and T_r planes of R, `stride` elements apart.
-// Every access names a plane, a per-thread byte offset `v` (the node's place
-// inside an x-y plane) and a workgroup-uniform byte offset `s` (the z plane).
-//  BUF = true: two buffer resources per copy (planes below plane 14, and the
-//  rest); the plane and z offsets go into the scalar offset, the x-y offset
-//  is the one vector offset, so loads and stores cost no vector address
-//  arithmetic.  Needs each half to span less than 4 GiB.
+// Access to the planes of the two ping-pong copies.
+//
+// Plain layout (4- and 8-byte elements): 26 population planes of T, `stride`
+// elements apart, then (deviation formats) the rho_r and T_r planes of R.
+//
+// Paired layout (2-byte elements): populations 2p and 2p+1 share one plane of
+// 32-bit words (population order f_0..f_18, g_0..g_6, then rho_r, T_r when
+// they are 16-bit too), so a node's values arrive in 14 four-byte loads
+// instead of 28 two-byte ones.  The step kernel is limited by how many loads
+// it keeps in flight; with two-byte loads that limit halves the bytes moved.
+// Stores stay 16-bit: the two halves of a word are written by different
+// neighbours.  32-bit references (BF16) follow the 13 pair planes.
+//
+// Every access names a population (or reference) index, a per-thread byte
+// offset `v` (the node's place inside an x-y plane) and a workgroup-uniform
+// byte offset `s` (the z plane), both counted in node strides of the layout
+// (4 bytes per node in a pair plane).
+//  BUF = true: two buffer resources per copy (planes below byte offset
+//  14 * stride * sizeof(T), and the rest); plane and z offsets go into the
+//  scalar offset, the x-y offset is the one vector offset and the half of a
+//  word a constant, so loads and stores cost no vector address arithmetic.
+//  Needs each half to span less than 4 GiB.
 //  BUF = false: plain global pointers (any size).
+template <typename T>
+constexpr bool paired_layout() { return sizeof(T) == 2; }
+
 template <typename T, typename R, bool BUF>
 struct PopIO;
 
 template <typename T, typename R>
 struct PopIO<T, R, true> {
+    static constexpr bool PAIR = paired_layout<T>();
     __amdgpu_buffer_rsrc_t in_lo, in_hi, out_lo, out_hi;
-    unsigned sb;   // population plane stride in bytes
+    unsigned sb;   // population plane stride in bytes (plain layout) or pair plane stride / 2
     unsigned rsb;  // reference plane stride in bytes
     __device__ PopIO(const T *pin, T *pout, size_t stride) {
         sb = (unsigned)(stride * sizeof(T));
@@ -364,44 +381,80 @@ struct PopIO<T, R, true> {
         out_lo = __builtin_amdgcn_make_buffer_rsrc(pout, 0, -1, kBufferFlags);
         out_hi = __builtin_amdgcn_make_buffer_rsrc(pout + kSplitPlane * stride, 0, -1, kBufferFlags);
     }
+    // Byte offset of the plane holding population a from the base of its
+    // resource (a < 14: low resource).  In the paired layout population a
+    // lives in pair plane a/2, which spans 2 sb bytes.
+    __device__ static constexpr bool low(int a) { return a < kSplitPlane; }
+    __device__ unsigned plane_off(int a) const {
+        const int b = low(a) ? a : a - kSplitPlane;
+        return PAIR ? (unsigned)(b >> 1) * 2u * sb : (unsigned)b * sb;
+    }
     __device__ T load(int a, unsigned v, unsigned s) const {
-        return a < kSplitPlane ? buf_ld<T>(in_lo, v, (unsigned)a * sb + s)
-                               : buf_ld<T>(in_hi, v, (unsigned)(a - kSplitPlane) * sb + s);
+        const unsigned half = PAIR ? (unsigned)(a & 1) * 2u : 0u;
+        return low(a) ? buf_ld<T>(in_lo, v + half, plane_off(a) + s) : buf_ld<T>(in_hi, v + half, plane_off(a) + s);
+    }
+    // Both halves of pair plane p (populations 2p, 2p+1), paired layout only.
+    __device__ unsigned load_pair(int p, unsigned v, unsigned s) const {
+        return low(2 * p) ? buf_ld<unsigned>(in_lo, v, plane_off(2 * p) + s)
+                          : buf_ld<unsigned>(in_hi, v, plane_off(2 * p) + s);
     }
     __device__ void store(int a, unsigned v, unsigned s, T x) const {
-        if (a < kSplitPlane) buf_st<T>(x, out_lo, v, (unsigned)a * sb + s);
-        else buf_st<T>(x, out_hi, v, (unsigned)(a - kSplitPlane) * sb + s);
+        const unsigned half = PAIR ? (unsigned)(a & 1) * 2u : 0u;
+        if (low(a)) buf_st<T>(x, out_lo, v + half, plane_off(a) + s);
+        else buf_st<T>(x, out_hi, v + half, plane_off(a) + s);
     }
-    // reference plane k (0: rho_r, 1: T_r); offsets in units of sizeof(R)
+    // Reference plane k (0: rho_r, 1: T_r).  16-bit references are the
+    // halves of the last pair plane; wider ones follow the population planes
+    // with offsets counted in sizeof(R).
     __device__ R load_ref(int k, unsigned v, unsigned s) const {
-        return buf_ld<R>(in_hi, v, (unsigned)(kPopPlanes - kSplitPlane) * sb + (unsigned)k * rsb + s);
+        if constexpr (sizeof(R) == 2) return __builtin_bit_cast(R, load(kPopPlanes + k, v, s));
+        else return buf_ld<R>(in_hi, v, (unsigned)(kPopPlanes - kSplitPlane) * sb + (unsigned)k * rsb + s);
     }
     __device__ void store_ref(int k, unsigned v, unsigned s, R x) const {
-        buf_st<R>(x, out_hi, v, (unsigned)(kPopPlanes - kSplitPlane) * sb + (unsigned)k * rsb + s);
+        if constexpr (sizeof(R) == 2) store(kPopPlanes + k, v, s, __builtin_bit_cast(T, x));
+        else buf_st<R>(x, out_hi, v, (unsigned)(kPopPlanes - kSplitPlane) * sb + (unsigned)k * rsb + s);
     }
 };
 
 template <typename T, typename R>
 struct PopIO<T, R, false> {
+    static constexpr bool PAIR = paired_layout<T>();
     const T *in;
     T *out;
     size_t st;
     __device__ PopIO(const T *pin, T *pout, size_t stride) : in(pin), out(pout), st(stride) {}
+    __device__ size_t plane_elems(int a) const { return PAIR ? (size_t)(a >> 1) * 2 * st + (a & 1) : a * st; }
     __device__ T load(int a, unsigned v, unsigned s) const {
-        return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(in + a * st) + s + v);
+        return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(in + plane_elems(a)) + s + v);
+    }
+    __device__ unsigned load_pair(int p, unsigned v, unsigned s) const {
+        return *reinterpret_cast<const unsigned *>(reinterpret_cast<const char *>(in + plane_elems(2 * p)) + s + v);
     }
     __device__ void store(int a, unsigned v, unsigned s, T x) const {
-        *reinterpret_cast<T *>(reinterpret_cast<char *>(out + a * st) + s + v) = x;
+        *reinterpret_cast<T *>(reinterpret_cast<char *>(out + plane_elems(a)) + s + v) = x;
     }
     __device__ R load_ref(int k, unsigned v, unsigned s) const {
+        if constexpr (sizeof(R) == 2) return __builtin_bit_cast(R, load(kPopPlanes + k, v, s));
         const R *base = reinterpret_cast<const R *>(in + kPopPlanes * st) + k * st;
         return *reinterpret_cast<const R *>(reinterpret_cast<const char *>(base) + s + v);
     }
     __device__ void store_ref(int k, unsigned v, unsigned s, R x) const {
-        R *base = reinterpret_cast<R *>(out + kPopPlanes * st) + k * st;
-        *reinterpret_cast<R *>(reinterpret_cast<char *>(base) + s + v) = x;
+        if constexpr (sizeof(R) == 2) {
+            store(kPopPlanes + k, v, s, __builtin_bit_cast(T, x));
+        } else {
+            R *base = reinterpret_cast<R *>(out + kPopPlanes * st) + k * st;
+            *reinterpret_cast<R *>(reinterpret_cast<char *>(base) + s + v) = x;
+        }
     }
 };
+
+// Element index of population a (or reference plane 26 + k) of node i in a
+// copy, for the one-thread-per-node helper kernels.
+template <typename T>
+__host__ __device__ inline size_t element_index(int a, size_t st, size_t i) {
+    if constexpr (paired_layout<T>()) return (size_t)(a >> 1) * 2 * st + 2 * i + (a & 1);
+    else return (size_t)a * st + i;
+}
 
 template <typename ST>
 struct StepArgs {
@@ -444,9 +497,12 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     constexpr C K = ST::kScale, IK = C(1) / ST::kScale;
     constexpr int NT = TX * TY, EX = TX + 2, EY = TY + 2, NE = EX * EY, NH = NE - NT;
     static_assert(NH <= NT, "halo must not exceed the tile");
-    constexpr unsigned ES = sizeof(E);
+    constexpr bool PAIR = paired_layout<E>();
+    constexpr unsigned NS = PAIR ? 4 : sizeof(E);  // bytes between neighbouring nodes of a plane
     constexpr int G0 = 19;  // first D3Q7 plane
     constexpr unsigned RSZ = sizeof(typename ST::R);
+    // node stride of the reference planes: 16-bit references share a pair plane
+    constexpr unsigned RU = (sizeof(typename ST::R) == 2 && paired_layout<E>()) ? 4 : RSZ;
     // References in the compute type need no LDS copy of rho of their own.
     constexpr bool OWN_RREF = DEV && sizeof(typename ST::R) != sizeof(C);
     constexpr int RS = OWN_RREF ? 4 : 1, RN = OWN_RREF ? NE : 1;
@@ -514,16 +570,45 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
 
     // Node `row` (index inside an x-y plane) of the plane starting at node zoff.
     auto load_node = [&](unsigned row, unsigned zoff, NodePops<C> &n) {
+        if constexpr (PAIR) {
+            // 13 words hold f_0..f_18, g_0..g_6; 16-bit references are the 14th.
+            constexpr int words = sizeof(typename ST::R) == 2 ? 14 : 13;
 #pragma unroll
-        for (int a = 0; a < 19; ++a) n.e[a] = ST::dec(io.load(a, row * ES, zoff * ES));
+            for (int p = 0; p < words; ++p) {
+                const unsigned w = io.load_pair(p, row * NS, zoff * NS);
+                const E lo = __builtin_bit_cast(E, (unsigned short)(w & 0xffffu));
+                const E hi = __builtin_bit_cast(E, (unsigned short)(w >> 16));
 #pragma unroll
-        for (int a = 0; a < 7; ++a) n.r[a] = ST::dec(io.load(G0 + a, row * ES, zoff * ES));
-        if constexpr (DEV) {
-            n.br = ST::rdec(io.load_ref(0, row * RSZ, zoff * RSZ));
-            n.bt = ST::rdec(io.load_ref(1, row * RSZ, zoff * RSZ));
+                for (int h = 0; h < 2; ++h) {
+                    const int a = 2 * p + h;
+                    const E x = h ? hi : lo;
+                    if (a < 19) {
+                        n.e[a] = ST::dec(x);
+                    } else if (a < 26) {
+                        n.r[a - 19] = ST::dec(x);
+                    } else if constexpr (sizeof(typename ST::R) == 2) {
+                        const C ref = ST::rdec(__builtin_bit_cast(typename ST::R, x));
+                        if (a == 26) n.br = ref;
+                        else n.bt = ref;
+                    }
+                }
+            }
+            if constexpr (sizeof(typename ST::R) != 2) {
+                n.br = ST::rdec(io.load_ref(0, row * RSZ, zoff * RSZ));
+                n.bt = ST::rdec(io.load_ref(1, row * RSZ, zoff * RSZ));
+            }
         } else {
-            n.br = C(0);
-            n.bt = C(0);
+#pragma unroll
+            for (int a = 0; a < 19; ++a) n.e[a] = ST::dec(io.load(a, row * NS, zoff * NS));
+#pragma unroll
+            for (int a = 0; a < 7; ++a) n.r[a] = ST::dec(io.load(G0 + a, row * NS, zoff * NS));
+            if constexpr (DEV) {
+                n.br = ST::rdec(io.load_ref(0, row * RSZ, zoff * RSZ));
+                n.bt = ST::rdec(io.load_ref(1, row * RSZ, zoff * RSZ));
+            } else {
+                n.br = C(0);
+                n.bt = C(0);
+            }
         }
     };
     // State of plane zp for this thread's tile node and its halo node.
@@ -572,8 +657,8 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     // Streaming byte offsets inside a plane (periodic in x and y).
     const int xm = xw == 0 ? nx - 1 : xw - 1, xp = xw == nx - 1 ? 0 : xw + 1;
     const int ym = yw == 0 ? ny - 1 : yw - 1, yp = yw == ny - 1 ? 0 : yw + 1;
-    const unsigned Xo[3] = {(unsigned)xm * ES, (unsigned)xw * ES, (unsigned)xp * ES};
-    const unsigned Yo[3] = {(unsigned)ym * nx * ES, (unsigned)yw * nx * ES, (unsigned)yp * nx * ES};
+    const unsigned Xo[3] = {(unsigned)xm * NS, (unsigned)xw * NS, (unsigned)xp * NS};
+    const unsigned Yo[3] = {(unsigned)ym * nx * NS, (unsigned)yw * nx * NS, (unsigned)yp * nx * NS};
     C T_bottom = C(0);
     if (WALLS) {
         const double dx = xw - P.cx, dy = yw - P.cy;
@@ -749,7 +834,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         }
 
         // ---- streaming (push), Eq. (4) and Eq. (40) ----
-        const unsigned PB = plane * ES;
+        const unsigned PB = plane * NS;
         const unsigned Zc = (unsigned)z * PB;
         unsigned Zo[3];
         if (WALLS) {
@@ -761,7 +846,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
             Zo[1] = Zc;
             Zo[2] = (unsigned)(z == nz - 1 ? 0 : z + 1) * PB;
         }
-        const unsigned rowb = irow * ES;
+        const unsigned rowb = irow * NS;
         // Values stored for the D3Q19 population a bound for the node in ring
         // slot `slot` at offset (dx, dy).  Plain storage keeps f* (the rest
         // part r0 closes the sum exactly: the rounded 1/3 + 6/18 + 12/36 is
@@ -857,8 +942,8 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
             }
         }
         if constexpr (DEV) {
-            io.store_ref(0, irow * RSZ, (unsigned)z * plane * RSZ, ST::renc(rho));
-            io.store_ref(1, irow * RSZ, (unsigned)z * plane * RSZ, ST::renc(T));
+            io.store_ref(0, irow * RU, (unsigned)z * plane * RU, ST::renc(rho));
+            io.store_ref(1, irow * RU, (unsigned)z * plane * RU, ST::renc(T));
         }
         if (P.gravity) rho_sum += (double)rho;
     };
@@ -980,9 +1065,11 @@ template <typename ST>
 struct NodeView {
     const typename ST::T *pop;
     size_t st;
-    __device__ double e(int a, size_t i) const { return ST::ddec(pop[a * st + i]); }
+    __device__ double e(int a, size_t i) const { return ST::ddec(pop[element_index<typename ST::T>(a, st, i)]); }
     __device__ double ref(int k, size_t i) const {
-        if constexpr (ST::kDev) {
+        if constexpr (ST::kDev && sizeof(typename ST::R) == sizeof(typename ST::T)) {
+            return (double)ST::rdec(__builtin_bit_cast(typename ST::R, pop[element_index<typename ST::T>(kPopPlanes + k, st, i)]));
+        } else if constexpr (ST::kDev) {
             const typename ST::R *refs = reinterpret_cast<const typename ST::R *>(pop + kPopPlanes * st);
             return (double)ST::rdec(refs[k * st + i]);
         }
@@ -1006,18 +1093,25 @@ __global__ void __launch_bounds__(256) k_init(const double *__restrict__ stage, 
     equilibrium19(rho, ux, uy, uz, meq);
     populations19(meq, fl);
     double br = 0.0, bt = 0.0;
+    using T_ = typename ST::T;
+    using R_ = typename ST::R;
     if constexpr (ST::kDev) {
         br = (double)ST::rdec(ST::renc((float)rho));
         bt = (double)ST::rdec(ST::renc((float)T));
-        typename ST::R *refs = reinterpret_cast<typename ST::R *>(pop + kPopPlanes * st);
-        refs[i] = ST::renc((float)rho);
-        refs[st + i] = ST::renc((float)T);
+        if constexpr (sizeof(R_) == sizeof(T_)) {
+            pop[element_index<T_>(kPopPlanes, st, i)] = __builtin_bit_cast(T_, ST::renc((float)rho));
+            pop[element_index<T_>(kPopPlanes + 1, st, i)] = __builtin_bit_cast(T_, ST::renc((float)T));
+        } else {
+            R_ *refs = reinterpret_cast<R_ *>(pop + kPopPlanes * st);
+            refs[i] = ST::renc((float)rho);
+            refs[st + i] = ST::renc((float)T);
+        }
     }
 #pragma unroll
-    for (int a = 0; a < 19; ++a) pop[a * st + i] = ST::denc(fl[a] - w19(a) * br);
-    pop[19 * st + i] = ST::denc(P.wT0 * (T - bt));
+    for (int a = 0; a < 19; ++a) pop[element_index<T_>(a, st, i)] = ST::denc(fl[a] - w19(a) * br);
+    pop[element_index<T_>(19, st, i)] = ST::denc(P.wT0 * (T - bt));
 #pragma unroll
-    for (int a = 1; a < 7; ++a) pop[(19 + a) * st + i] = ST::denc(P.wT1 * (T - bt));
+    for (int a = 1; a < 7; ++a) pop[element_index<T_>(19 + a, st, i)] = ST::denc(P.wT1 * (T - bt));
     phi[i] = typename ST::C(0);
 }
 
