@@ -29,6 +29,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace lbm {
 
 // Sec. II, Eq. (2): D3Q19 velocity components, alpha = 0..18.
@@ -343,13 +345,17 @@ constexpr int kPopPlanes = 26;
 // Plain layout (4- and 8-byte elements): 26 population planes of T, `stride`
 // elements apart, then (deviation formats) the rho_r and T_r planes of R.
 //
-// Paired layout (2-byte elements): populations 2p and 2p+1 share one plane of
-// 32-bit words (population order f_0..f_18, g_0..g_6, then rho_r, T_r when
-// they are 16-bit too), so a node's values arrive in 14 four-byte loads
-// instead of 28 two-byte ones.  The step kernel is limited by how many loads
-// it keeps in flight; with two-byte loads that limit halves the bytes moved.
-// Stores stay 16-bit: the two halves of a word are written by different
-// neighbours.  32-bit references (BF16) follow the 13 pair planes.
+// Paired layout (2-byte elements): two populations share one plane of 32-bit
+// words, so a node's values arrive in 14 four-byte loads instead of 28
+// two-byte ones (the step kernel is limited by how many loads it keeps in
+// flight, and two-byte loads halve the bytes each one moves).  The pairs are
+// chosen for the push stores: f_a and g_a of the same velocity (a = 0..6)
+// go to the same neighbour and are written as one word; the diagonal f pair
+// up with a partner of the same e_z, whose half is written in the same
+// z-plane pass, so both halves of a word reach L2 close together; 16-bit
+// references (rho_r, T_r) form the last pair.  32-bit references (BF16)
+// follow the 13 pair planes.  Population index a: 0..18 f, 19..25 g, 26..27
+// the references.
 //
 // Every access names a population (or reference) index, a per-thread byte
 // offset `v` (the node's place inside an x-y plane) and a workgroup-uniform
@@ -363,6 +369,23 @@ constexpr int kPopPlanes = 26;
 //  BUF = false: plain global pointers (any size).
 template <typename T>
 constexpr bool paired_layout() { return sizeof(T) == 2; }
+
+// Members (low half, high half) of pair plane p, and the pair and half of
+// population a.
+constexpr int kPairMember[14][2] = {{0, 19}, {1, 20}, {2, 21}, {3, 22}, {4, 23}, {5, 24}, {6, 25},
+                                    {7, 8},  {9, 10}, {11, 14}, {15, 18}, {12, 13}, {16, 17}, {26, 27}};
+constexpr int kPairOf[28] = {0, 1, 2, 3, 4, 5, 6, 7, 7, 8, 8, 9, 11, 11, 9, 10, 12, 12, 10,
+                             0, 1, 2, 3, 4, 5, 6, 13, 13};
+constexpr int kHalfOf[28] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 0, 1, 0, 0, 1, 1, 0, 0, 1, 1,
+                             1, 1, 1, 1, 1, 1, 1, 0, 1};
+constexpr bool pair_tables_consistent() {
+    for (int p = 0; p < 14; ++p)
+        for (int h = 0; h < 2; ++h)
+            if (kPairOf[kPairMember[p][h]] != p || kHalfOf[kPairMember[p][h]] != h) return false;
+    return true;
+}
+static_assert(pair_tables_consistent(), "pair tables disagree");
+constexpr int kPairSplit = kSplitPlane / 2;  // pairs [0,7) behind the low resource
 
 template <typename T, typename R, bool BUF>
 struct PopIO;
@@ -381,27 +404,36 @@ struct PopIO<T, R, true> {
         out_lo = __builtin_amdgcn_make_buffer_rsrc(pout, 0, -1, kBufferFlags);
         out_hi = __builtin_amdgcn_make_buffer_rsrc(pout + kSplitPlane * stride, 0, -1, kBufferFlags);
     }
-    // Byte offset of the plane holding population a from the base of its
-    // resource (a < 14: low resource).  In the paired layout population a
-    // lives in pair plane a/2, which spans 2 sb bytes.
-    __device__ static constexpr bool low(int a) { return a < kSplitPlane; }
+    // Whether population a sits behind the low resource, and the byte offset
+    // of its plane from that resource's base (pair plane kPairOf[a], 2 sb
+    // bytes wide, in the paired layout).
+    __device__ static constexpr bool low(int a) { return PAIR ? kPairOf[a] < kPairSplit : a < kSplitPlane; }
     __device__ unsigned plane_off(int a) const {
-        const int b = low(a) ? a : a - kSplitPlane;
-        return PAIR ? (unsigned)(b >> 1) * 2u * sb : (unsigned)b * sb;
+        if constexpr (PAIR) {
+            const int p = kPairOf[a];
+            return (unsigned)(p < kPairSplit ? p : p - kPairSplit) * 2u * sb;
+        } else {
+            return (unsigned)(a < kSplitPlane ? a : a - kSplitPlane) * sb;
+        }
     }
+    __device__ static constexpr unsigned half_off(int a) { return PAIR ? (unsigned)kHalfOf[a] * 2u : 0u; }
     __device__ T load(int a, unsigned v, unsigned s) const {
-        const unsigned half = PAIR ? (unsigned)(a & 1) * 2u : 0u;
-        return low(a) ? buf_ld<T>(in_lo, v + half, plane_off(a) + s) : buf_ld<T>(in_hi, v + half, plane_off(a) + s);
+        return low(a) ? buf_ld<T>(in_lo, v + half_off(a), plane_off(a) + s)
+                      : buf_ld<T>(in_hi, v + half_off(a), plane_off(a) + s);
     }
-    // Both halves of pair plane p (populations 2p, 2p+1), paired layout only.
+    // Both halves of pair plane p (paired layout only).
     __device__ unsigned load_pair(int p, unsigned v, unsigned s) const {
-        return low(2 * p) ? buf_ld<unsigned>(in_lo, v, plane_off(2 * p) + s)
-                          : buf_ld<unsigned>(in_hi, v, plane_off(2 * p) + s);
+        const int a = kPairMember[p][0];
+        return low(a) ? buf_ld<unsigned>(in_lo, v, plane_off(a) + s) : buf_ld<unsigned>(in_hi, v, plane_off(a) + s);
     }
     __device__ void store(int a, unsigned v, unsigned s, T x) const {
-        const unsigned half = PAIR ? (unsigned)(a & 1) * 2u : 0u;
-        if (low(a)) buf_st<T>(x, out_lo, v + half, plane_off(a) + s);
-        else buf_st<T>(x, out_hi, v + half, plane_off(a) + s);
+        if (low(a)) buf_st<T>(x, out_lo, v + half_off(a), plane_off(a) + s);
+        else buf_st<T>(x, out_hi, v + half_off(a), plane_off(a) + s);
+    }
+    __device__ void store_pair(int p, unsigned v, unsigned s, unsigned w) const {
+        const int a = kPairMember[p][0];
+        if (low(a)) buf_st<unsigned>(w, out_lo, v, plane_off(a) + s);
+        else buf_st<unsigned>(w, out_hi, v, plane_off(a) + s);
     }
     // Reference plane k (0: rho_r, 1: T_r).  16-bit references are the
     // halves of the last pair plane; wider ones follow the population planes
@@ -423,15 +455,20 @@ struct PopIO<T, R, false> {
     T *out;
     size_t st;
     __device__ PopIO(const T *pin, T *pout, size_t stride) : in(pin), out(pout), st(stride) {}
-    __device__ size_t plane_elems(int a) const { return PAIR ? (size_t)(a >> 1) * 2 * st + (a & 1) : a * st; }
+    __device__ size_t plane_elems(int a) const {
+        return PAIR ? (size_t)kPairOf[a] * 2 * st + kHalfOf[a] : a * st;
+    }
     __device__ T load(int a, unsigned v, unsigned s) const {
         return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(in + plane_elems(a)) + s + v);
     }
     __device__ unsigned load_pair(int p, unsigned v, unsigned s) const {
-        return *reinterpret_cast<const unsigned *>(reinterpret_cast<const char *>(in + plane_elems(2 * p)) + s + v);
+        return *reinterpret_cast<const unsigned *>(reinterpret_cast<const char *>(in + (size_t)p * 2 * st) + s + v);
     }
     __device__ void store(int a, unsigned v, unsigned s, T x) const {
         *reinterpret_cast<T *>(reinterpret_cast<char *>(out + plane_elems(a)) + s + v) = x;
+    }
+    __device__ void store_pair(int p, unsigned v, unsigned s, unsigned w) const {
+        *reinterpret_cast<unsigned *>(reinterpret_cast<char *>(out + (size_t)p * 2 * st) + s + v) = w;
     }
     __device__ R load_ref(int k, unsigned v, unsigned s) const {
         if constexpr (sizeof(R) == 2) return __builtin_bit_cast(R, load(kPopPlanes + k, v, s));
@@ -452,7 +489,7 @@ struct PopIO<T, R, false> {
 // copy, for the one-thread-per-node helper kernels.
 template <typename T>
 __host__ __device__ inline size_t element_index(int a, size_t st, size_t i) {
-    if constexpr (paired_layout<T>()) return (size_t)(a >> 1) * 2 * st + 2 * i + (a & 1);
+    if constexpr (paired_layout<T>()) return (size_t)kPairOf[a] * 2 * st + 2 * i + kHalfOf[a];
     else return (size_t)a * st + i;
 }
 
@@ -484,6 +521,17 @@ __device__ __forceinline__ int xcd_logical_block(int b, int nb) {
 template <typename C>
 struct NodePops {
     C e[19], r[7], br, bt;
+};
+
+// A node's state as it arrives from memory in the paired layout: the 32-bit
+// words (13 of population pairs, a 14th of 16-bit references) and, for
+// 32-bit references, the references in the compute type.  Planes in flight
+// are kept in this form and decoded where they are used, which halves the
+// registers they occupy.
+template <typename C, int WORDS>
+struct NodeWords {
+    unsigned w[WORDS];
+    C br, bt;
 };
 
 // One workgroup's share of a time step: the x-y tile and z chunk with index
@@ -568,31 +616,46 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         return zz < 0 ? zz + nz : zz;
     };
 
-    // Node `row` (index inside an x-y plane) of the plane starting at node zoff.
-    auto load_node = [&](unsigned row, unsigned zoff, NodePops<C> &n) {
+    // 13 words hold f_0..f_18, g_0..g_6; 16-bit references are the 14th.
+    constexpr int WORDS = sizeof(typename ST::R) == 2 ? 14 : 13;
+    using Node = std::conditional_t<PAIR, NodeWords<C, WORDS>, NodePops<C>>;
+    // The node's values in the compute type.
+    auto decode = [&](const Node &n) -> NodePops<C> {
         if constexpr (PAIR) {
-            // 13 words hold f_0..f_18, g_0..g_6; 16-bit references are the 14th.
-            constexpr int words = sizeof(typename ST::R) == 2 ? 14 : 13;
+            NodePops<C> d;
 #pragma unroll
-            for (int p = 0; p < words; ++p) {
-                const unsigned w = io.load_pair(p, row * NS, zoff * NS);
-                const E lo = __builtin_bit_cast(E, (unsigned short)(w & 0xffffu));
-                const E hi = __builtin_bit_cast(E, (unsigned short)(w >> 16));
+            for (int p = 0; p < WORDS; ++p) {
+                const E lo = __builtin_bit_cast(E, (unsigned short)(n.w[p] & 0xffffu));
+                const E hi = __builtin_bit_cast(E, (unsigned short)(n.w[p] >> 16));
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    const int a = 2 * p + h;
+                    const int a = kPairMember[p][h];
                     const E x = h ? hi : lo;
                     if (a < 19) {
-                        n.e[a] = ST::dec(x);
+                        d.e[a] = ST::dec(x);
                     } else if (a < 26) {
-                        n.r[a - 19] = ST::dec(x);
+                        d.r[a - 19] = ST::dec(x);
                     } else if constexpr (sizeof(typename ST::R) == 2) {
                         const C ref = ST::rdec(__builtin_bit_cast(typename ST::R, x));
-                        if (a == 26) n.br = ref;
-                        else n.bt = ref;
+                        if (a == 26) d.br = ref;
+                        else d.bt = ref;
                     }
                 }
             }
+            if constexpr (sizeof(typename ST::R) != 2) {
+                d.br = n.br;
+                d.bt = n.bt;
+            }
+            return d;
+        } else {
+            return n;
+        }
+    };
+    // Node `row` (index inside an x-y plane) of the plane starting at node zoff.
+    auto load_node = [&](unsigned row, unsigned zoff, Node &n) {
+        if constexpr (PAIR) {
+#pragma unroll
+            for (int p = 0; p < WORDS; ++p) n.w[p] = io.load_pair(p, row * NS, zoff * NS);
             if constexpr (sizeof(typename ST::R) != 2) {
                 n.br = ST::rdec(io.load_ref(0, row * RSZ, zoff * RSZ));
                 n.bt = ST::rdec(io.load_ref(1, row * RSZ, zoff * RSZ));
@@ -612,7 +675,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         }
     };
     // State of plane zp for this thread's tile node and its halo node.
-    auto load_plane = [&](int zp, NodePops<C> &k, NodePops<C> &h) {
+    auto load_plane = [&](int zp, Node &k, Node &h) {
         const unsigned zoff = (unsigned)zmap(zp) * plane;
         load_node(irow, zoff, k);
         if (has_halo) load_node(hrow, zoff, h);
@@ -629,7 +692,8 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     };
     // rho, T, psi (and the rounded references) of a loaded plane, tile node
     // and halo node, into LDS slot `slot`.
-    auto plane_moments = [&](int slot, const NodePops<C> &k, const NodePops<C> &h, C &krho, C &kT, C &kpsi) {
+    auto plane_moments = [&](int slot, const Node &kraw, const Node &hraw, C &krho, C &kT, C &kpsi) {
+        const NodePops<C> k = decode(kraw);
         const C rho = node_rho(k), T = node_T(k);
         const C p2 = psi_squared(P, rho, T);
         // Unstable node (rho <= 0, psi^2 < 0 or NaN): one flag update per wave.
@@ -645,6 +709,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         kT = T;
         kpsi = psi;
         if (has_halo) {
+            const NodePops<C> h = decode(hraw);
             const C hr = node_rho(h), hT = node_T(h);
             const C hp2 = psi_squared(P, hr, hT);
             s_psi[slot][hli] = Num<C>::sqrt(hp2 > C(0) ? hp2 : C(0));
@@ -671,7 +736,8 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     // holds plane z; s-1 and s+1 its neighbours).  All population-space
     // quantities (moments, equilibria, sources, post-collision values) are
     // carried K-scaled, so the stored values convert without a multiply.
-    auto collide_stream = [&](int z, int s, const NodePops<C> &nd, C rho, C T, C psi) {
+    auto collide_stream = [&](int z, int s, const Node &ndraw, C rho, C T, C psi) {
+        const NodePops<C> nd = decode(ndraw);
         const int sm = (s + 3) & 3, s0 = s & 3, sp = (s + 1) & 3;
         const int sl[3] = {sm, s0, sp};
         // Eq. (7) and the isotropic gradient: omega(1) = 1/6, omega(2) = 1/12.
@@ -878,21 +944,6 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
                 return ST::enc(fa[a]);
             }
         };
-#pragma unroll
-        for (int a = 0; a < 19; ++a) {
-            const int ex = kE19X[a], ey = kE19Y[a], ez = kE19Z[a];
-            const unsigned inrow = Yo[ey + 1] + Xo[ex + 1];
-            if (WALLS) {
-                if (ez < 0 && z == 0) {  // Eq. (50): halfway bounce-back into the own node
-                    io.store(opposite(a), rowb, Zc, ST::enc(fa[a]));
-                    continue;
-                }
-                if (ez > 0 && z == nz - 1) continue;  // leaves through the open top
-                if (ez < 0 && z == nz - 1)             // open top: unknown f copied from below
-                    io.store(a, inrow, Zc, fval(a, s0, ex, ey));
-            }
-            io.store(a, inrow, Zo[ez + 1], fval(a, sl[ez + 1], ex, ey));
-        }
         // D3Q7: g+ = w T_emit + gs; the deviation formats encode against the
         // destination's T_r as above.  A destination in the reservoir layer
         // receives w T_shell.
@@ -915,35 +966,83 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
                 return ga[a];
             }
         };
-        if (P.thermal) {
+        bool stored = false;
+        if constexpr (PAIR && !WALLS) {
+          if (P.thermal) {
+            stored = true;
+            // f_a and g_a of the same velocity (a = 0..6) go to the same
+            // neighbour and share a word of the paired layout: one store.
+            auto word = [](E lo, E hi) -> unsigned {
+                return (unsigned)__builtin_bit_cast(unsigned short, lo) |
+                       ((unsigned)__builtin_bit_cast(unsigned short, hi) << 16);
+            };
 #pragma unroll
             for (int a = 0; a < 7; ++a) {
-                const int ex = kE7X[a], ey = kE7Y[a], ez = kE7Z[a];
+                const int ex = kE19X[a], ey = kE19Y[a], ez = kE19Z[a];
+                const bool to_shell = xs[ex + 1] || ys[ey + 1] || zs[ez + 1];
+                io.store_pair(kPairOf[a], Yo[ey + 1] + Xo[ex + 1], Zo[ez + 1],
+                              word(fval(a, sl[ez + 1], ex, ey), ST::enc(gval(a, sl[ez + 1], ex, ey, to_shell))));
+            }
+#pragma unroll
+            for (int a = 7; a < 19; ++a) {
+                const int ex = kE19X[a], ey = kE19Y[a], ez = kE19Z[a];
+                io.store(a, Yo[ey + 1] + Xo[ex + 1], Zo[ez + 1], fval(a, sl[ez + 1], ex, ey));
+            }
+            if constexpr (sizeof(typename ST::R) == 2) {
+                io.store_pair(kPairOf[kPopPlanes], rowb, Zc,
+                              word(__builtin_bit_cast(E, ST::renc(rho)), __builtin_bit_cast(E, ST::renc(T))));
+            } else {
+                io.store_ref(0, irow * RU, (unsigned)z * plane * RU, ST::renc(rho));
+                io.store_ref(1, irow * RU, (unsigned)z * plane * RU, ST::renc(T));
+            }
+          }
+        }
+        if (!stored) {
+    #pragma unroll
+            for (int a = 0; a < 19; ++a) {
+                const int ex = kE19X[a], ey = kE19Y[a], ez = kE19Z[a];
+                const unsigned inrow = Yo[ey + 1] + Xo[ex + 1];
                 if (WALLS) {
-                    // Eq. (51): g_opp(x_b) = -g+_a(x_b) + 2 w T_w, into the own node
-                    const bool bottom = ez < 0 && z == 0, top = ez > 0 && z == nz - 1;
-                    if (bottom || top) {
-                        const C Tw = bottom ? T_bottom : (C)P.T_top;
-                        const C v = DEV ? fmad(K * P.wT1, C(2) * Tw - T - own_tref, -gs[a])
-                                        : fmad(C(2) * P.wT1, Tw, -ga[a]);
-                        io.store(G0 + opposite(a), rowb, Zc, ST::enc(v));
+                    if (ez < 0 && z == 0) {  // Eq. (50): halfway bounce-back into the own node
+                        io.store(opposite(a), rowb, Zc, ST::enc(fa[a]));
                         continue;
                     }
+                    if (ez > 0 && z == nz - 1) continue;  // leaves through the open top
+                    if (ez < 0 && z == nz - 1)             // open top: unknown f copied from below
+                        io.store(a, inrow, Zc, fval(a, s0, ex, ey));
                 }
-                const bool to_shell = xs[ex + 1] || ys[ey + 1] || zs[ez + 1];
-                io.store(G0 + a, Yo[ey + 1] + Xo[ex + 1], Zo[ez + 1], ST::enc(gval(a, sl[ez + 1], ex, ey, to_shell)));
+                io.store(a, inrow, Zo[ez + 1], fval(a, sl[ez + 1], ex, ey));
             }
-        } else {
-            // temperature held fixed: g stays at the node (re-encoded against the new reference)
-#pragma unroll
-            for (int a = 0; a < 7; ++a) {
-                const C v = DEV ? fmad(K * (a == 0 ? P.wT0 : P.wT1), nd.bt - own_tref, nd.r[a]) : nd.r[a];
-                io.store(G0 + a, rowb, Zc, ST::enc(v));
+            if (P.thermal) {
+    #pragma unroll
+                for (int a = 0; a < 7; ++a) {
+                    const int ex = kE7X[a], ey = kE7Y[a], ez = kE7Z[a];
+                    if (WALLS) {
+                        // Eq. (51): g_opp(x_b) = -g+_a(x_b) + 2 w T_w, into the own node
+                        const bool bottom = ez < 0 && z == 0, top = ez > 0 && z == nz - 1;
+                        if (bottom || top) {
+                            const C Tw = bottom ? T_bottom : (C)P.T_top;
+                            const C v = DEV ? fmad(K * P.wT1, C(2) * Tw - T - own_tref, -gs[a])
+                                            : fmad(C(2) * P.wT1, Tw, -ga[a]);
+                            io.store(G0 + opposite(a), rowb, Zc, ST::enc(v));
+                            continue;
+                        }
+                    }
+                    const bool to_shell = xs[ex + 1] || ys[ey + 1] || zs[ez + 1];
+                    io.store(G0 + a, Yo[ey + 1] + Xo[ex + 1], Zo[ez + 1], ST::enc(gval(a, sl[ez + 1], ex, ey, to_shell)));
+                }
+            } else {
+                // temperature held fixed: g stays at the node (re-encoded against the new reference)
+    #pragma unroll
+                for (int a = 0; a < 7; ++a) {
+                    const C v = DEV ? fmad(K * (a == 0 ? P.wT0 : P.wT1), nd.bt - own_tref, nd.r[a]) : nd.r[a];
+                    io.store(G0 + a, rowb, Zc, ST::enc(v));
+                }
             }
-        }
-        if constexpr (DEV) {
-            io.store_ref(0, irow * RU, (unsigned)z * plane * RU, ST::renc(rho));
-            io.store_ref(1, irow * RU, (unsigned)z * plane * RU, ST::renc(T));
+            if constexpr (DEV) {
+                io.store_ref(0, irow * RU, (unsigned)z * plane * RU, ST::renc(rho));
+                io.store_ref(1, irow * RU, (unsigned)z * plane * RU, ST::renc(T));
+            }
         }
         if (P.gravity) rho_sum += (double)rho;
     };
@@ -955,10 +1054,10 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     // (Issuing them earlier would put more memory operations between a load
     // and its use than the vmcnt counter can express, which forces a full
     // drain.)
-    NodePops<C> cur, nxt, nxh, nq, nqh;  // plane z; plane z+1 (tile, halo); plane z+2
+    Node cur, nxt, nxh, nq, nqh;  // plane z; plane z+1 (tile, halo); plane z+2
     C c_rho, c_T, c_psi, n_rho, n_T, n_psi;
     {
-        NodePops<C> t0, th0, h0;
+        Node t0, th0, h0;
         C a0, a1, a2;
         load_plane(z0 - 1, t0, th0);
         load_plane(z0, cur, h0);
