@@ -82,24 +82,25 @@ size_t max_workgroups(const lbm_params *p) {
 
 size_t copy_bytes(const Layout &L) { return L.stride * (26 * L.es + (L.planes - 26) * L.rs); }
 
-// Physical planes of a copy, as stored: the plain layout has the 26
-// population planes and (deviation formats) the two reference planes; the
-// paired layout of 16-bit formats has 13 planes of population pairs, then
-// one pair plane of 16-bit references or two planes of 32-bit ones.
-bool paired(const Layout &L) { return L.es == 2; }
+// Physical planes of a copy, as stored: the plain layout (FP64) has the 26
+// population planes; the paired layout (2- and 4-byte elements) has 13
+// planes of population pairs, then (deviation formats) one pair plane of
+// references as wide as the populations, or two planes of wider ones.
+bool paired(const Layout &L) { return L.es == 2 || L.es == 4; }
+bool refs_in_pair(const Layout &L) { return L.planes == 28 && L.rs == L.es; }
 size_t phys_planes(const Layout &L) {
     if (!paired(L)) return L.planes;
-    return 13 + (L.rs == 2 ? 1 : 2);
+    return 13 + (L.planes == 28 ? (refs_in_pair(L) ? 1 : 2) : 0);
 }
 size_t plane_offset(const Layout &L, size_t k) {
     if (paired(L)) {
-        if (k < 13 || L.rs == 2) return k * L.stride * 4;
+        if (k < 13 || refs_in_pair(L)) return k * L.stride * 2 * L.es;
         return 26 * L.stride * L.es + (k - 13) * L.stride * L.rs;
     }
     return k < 26 ? k * L.stride * L.es : 26 * L.stride * L.es + (k - 26) * L.stride * L.rs;
 }
 size_t plane_bytes(const Layout &L, size_t k) {
-    if (paired(L)) return L.nn * 4;
+    if (paired(L)) return (k < 13 || refs_in_pair(L)) ? L.nn * 2 * L.es : L.nn * L.rs;
     return L.nn * (k < 26 ? L.es : L.rs);
 }
 

@@ -368,7 +368,21 @@ constexpr int kPopPlanes = 26;
 //  Needs each half to span less than 4 GiB.
 //  BUF = false: plain global pointers (any size).
 template <typename T>
-constexpr bool paired_layout() { return sizeof(T) == 2; }
+constexpr bool paired_layout() { return sizeof(T) == 2 || sizeof(T) == 4; }
+
+// The word holding a pair of T, and packing/unpacking of its halves.
+template <typename T>
+using PairWord = std::conditional_t<sizeof(T) == 2, unsigned, unsigned long long>;
+template <typename T>
+__device__ __forceinline__ PairWord<T> pack_pair(T lo, T hi) {
+    using H = std::conditional_t<sizeof(T) == 2, unsigned short, unsigned>;
+    return (PairWord<T>)__builtin_bit_cast(H, lo) | ((PairWord<T>)__builtin_bit_cast(H, hi) << (8 * sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ T pair_half(PairWord<T> w, int h) {
+    using H = std::conditional_t<sizeof(T) == 2, unsigned short, unsigned>;
+    return __builtin_bit_cast(T, (H)(h ? w >> (8 * sizeof(T)) : w));
+}
 
 // Members (low half, high half) of pair plane p, and the pair and half of
 // population a.
@@ -416,34 +430,34 @@ struct PopIO<T, R, true> {
             return (unsigned)(a < kSplitPlane ? a : a - kSplitPlane) * sb;
         }
     }
-    __device__ static constexpr unsigned half_off(int a) { return PAIR ? (unsigned)kHalfOf[a] * 2u : 0u; }
+    __device__ static constexpr unsigned half_off(int a) { return PAIR ? (unsigned)(kHalfOf[a] * sizeof(T)) : 0u; }
     __device__ T load(int a, unsigned v, unsigned s) const {
         return low(a) ? buf_ld<T>(in_lo, v + half_off(a), plane_off(a) + s)
                       : buf_ld<T>(in_hi, v + half_off(a), plane_off(a) + s);
     }
     // Both halves of pair plane p (paired layout only).
-    __device__ unsigned load_pair(int p, unsigned v, unsigned s) const {
+    __device__ PairWord<T> load_pair(int p, unsigned v, unsigned s) const {
         const int a = kPairMember[p][0];
-        return low(a) ? buf_ld<unsigned>(in_lo, v, plane_off(a) + s) : buf_ld<unsigned>(in_hi, v, plane_off(a) + s);
+        return low(a) ? buf_ld<PairWord<T>>(in_lo, v, plane_off(a) + s) : buf_ld<PairWord<T>>(in_hi, v, plane_off(a) + s);
     }
     __device__ void store(int a, unsigned v, unsigned s, T x) const {
         if (low(a)) buf_st<T>(x, out_lo, v + half_off(a), plane_off(a) + s);
         else buf_st<T>(x, out_hi, v + half_off(a), plane_off(a) + s);
     }
-    __device__ void store_pair(int p, unsigned v, unsigned s, unsigned w) const {
+    __device__ void store_pair(int p, unsigned v, unsigned s, PairWord<T> w) const {
         const int a = kPairMember[p][0];
-        if (low(a)) buf_st<unsigned>(w, out_lo, v, plane_off(a) + s);
-        else buf_st<unsigned>(w, out_hi, v, plane_off(a) + s);
+        if (low(a)) buf_st<PairWord<T>>(w, out_lo, v, plane_off(a) + s);
+        else buf_st<PairWord<T>>(w, out_hi, v, plane_off(a) + s);
     }
-    // Reference plane k (0: rho_r, 1: T_r).  16-bit references are the
-    // halves of the last pair plane; wider ones follow the population planes
-    // with offsets counted in sizeof(R).
+    // Reference plane k (0: rho_r, 1: T_r).  References as wide as the
+    // populations are the halves of the last pair plane; wider ones follow
+    // the population planes with offsets counted in sizeof(R).
     __device__ R load_ref(int k, unsigned v, unsigned s) const {
-        if constexpr (sizeof(R) == 2) return __builtin_bit_cast(R, load(kPopPlanes + k, v, s));
+        if constexpr (PAIR && sizeof(R) == sizeof(T)) return __builtin_bit_cast(R, load(kPopPlanes + k, v, s));
         else return buf_ld<R>(in_hi, v, (unsigned)(kPopPlanes - kSplitPlane) * sb + (unsigned)k * rsb + s);
     }
     __device__ void store_ref(int k, unsigned v, unsigned s, R x) const {
-        if constexpr (sizeof(R) == 2) store(kPopPlanes + k, v, s, __builtin_bit_cast(T, x));
+        if constexpr (PAIR && sizeof(R) == sizeof(T)) store(kPopPlanes + k, v, s, __builtin_bit_cast(T, x));
         else buf_st<R>(x, out_hi, v, (unsigned)(kPopPlanes - kSplitPlane) * sb + (unsigned)k * rsb + s);
     }
 };
@@ -461,22 +475,22 @@ struct PopIO<T, R, false> {
     __device__ T load(int a, unsigned v, unsigned s) const {
         return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(in + plane_elems(a)) + s + v);
     }
-    __device__ unsigned load_pair(int p, unsigned v, unsigned s) const {
-        return *reinterpret_cast<const unsigned *>(reinterpret_cast<const char *>(in + (size_t)p * 2 * st) + s + v);
+    __device__ PairWord<T> load_pair(int p, unsigned v, unsigned s) const {
+        return *reinterpret_cast<const PairWord<T> *>(reinterpret_cast<const char *>(in + (size_t)p * 2 * st) + s + v);
     }
     __device__ void store(int a, unsigned v, unsigned s, T x) const {
         *reinterpret_cast<T *>(reinterpret_cast<char *>(out + plane_elems(a)) + s + v) = x;
     }
-    __device__ void store_pair(int p, unsigned v, unsigned s, unsigned w) const {
-        *reinterpret_cast<unsigned *>(reinterpret_cast<char *>(out + (size_t)p * 2 * st) + s + v) = w;
+    __device__ void store_pair(int p, unsigned v, unsigned s, PairWord<T> w) const {
+        *reinterpret_cast<PairWord<T> *>(reinterpret_cast<char *>(out + (size_t)p * 2 * st) + s + v) = w;
     }
     __device__ R load_ref(int k, unsigned v, unsigned s) const {
-        if constexpr (sizeof(R) == 2) return __builtin_bit_cast(R, load(kPopPlanes + k, v, s));
+        if constexpr (PAIR && sizeof(R) == sizeof(T)) return __builtin_bit_cast(R, load(kPopPlanes + k, v, s));
         const R *base = reinterpret_cast<const R *>(in + kPopPlanes * st) + k * st;
         return *reinterpret_cast<const R *>(reinterpret_cast<const char *>(base) + s + v);
     }
     __device__ void store_ref(int k, unsigned v, unsigned s, R x) const {
-        if constexpr (sizeof(R) == 2) {
+        if constexpr (PAIR && sizeof(R) == sizeof(T)) {
             store(kPopPlanes + k, v, s, __builtin_bit_cast(T, x));
         } else {
             R *base = reinterpret_cast<R *>(out + kPopPlanes * st) + k * st;
@@ -528,9 +542,9 @@ struct NodePops {
 // 32-bit references, the references in the compute type.  Planes in flight
 // are kept in this form and decoded where they are used, which halves the
 // registers they occupy.
-template <typename C, int WORDS>
+template <typename C, typename W, int WORDS>
 struct NodeWords {
-    unsigned w[WORDS];
+    W w[WORDS];
     C br, bt;
 };
 
@@ -546,11 +560,12 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     constexpr int NT = TX * TY, EX = TX + 2, EY = TY + 2, NE = EX * EY, NH = NE - NT;
     static_assert(NH <= NT, "halo must not exceed the tile");
     constexpr bool PAIR = paired_layout<E>();
-    constexpr unsigned NS = PAIR ? 4 : sizeof(E);  // bytes between neighbouring nodes of a plane
+    constexpr unsigned NS = PAIR ? 2 * sizeof(E) : sizeof(E);  // bytes between neighbouring nodes of a plane
     constexpr int G0 = 19;  // first D3Q7 plane
     constexpr unsigned RSZ = sizeof(typename ST::R);
     // node stride of the reference planes: 16-bit references share a pair plane
-    constexpr unsigned RU = (sizeof(typename ST::R) == 2 && paired_layout<E>()) ? 4 : RSZ;
+    constexpr bool REF_IN_PAIR = ST::kDev && sizeof(typename ST::R) == sizeof(E) && paired_layout<E>();
+    constexpr unsigned RU = REF_IN_PAIR ? 2 * sizeof(E) : RSZ;
     // References in the compute type need no LDS copy of rho of their own.
     constexpr bool OWN_RREF = DEV && sizeof(typename ST::R) != sizeof(C);
     constexpr int RS = OWN_RREF ? 4 : 1, RN = OWN_RREF ? NE : 1;
@@ -616,33 +631,32 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         return zz < 0 ? zz + nz : zz;
     };
 
-    // 13 words hold f_0..f_18, g_0..g_6; 16-bit references are the 14th.
-    constexpr int WORDS = sizeof(typename ST::R) == 2 ? 14 : 13;
-    using Node = std::conditional_t<PAIR, NodeWords<C, WORDS>, NodePops<C>>;
+    // 13 words hold f_0..f_18, g_0..g_6; references of the element's width
+    // are the 14th.
+    constexpr int WORDS = REF_IN_PAIR ? 14 : 13;
+    using Node = std::conditional_t<PAIR, NodeWords<C, PairWord<E>, WORDS>, NodePops<C>>;
     // The node's values in the compute type.
     auto decode = [&](const Node &n) -> NodePops<C> {
         if constexpr (PAIR) {
             NodePops<C> d;
 #pragma unroll
             for (int p = 0; p < WORDS; ++p) {
-                const E lo = __builtin_bit_cast(E, (unsigned short)(n.w[p] & 0xffffu));
-                const E hi = __builtin_bit_cast(E, (unsigned short)(n.w[p] >> 16));
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const int a = kPairMember[p][h];
-                    const E x = h ? hi : lo;
+                    const E x = pair_half<E>(n.w[p], h);
                     if (a < 19) {
                         d.e[a] = ST::dec(x);
                     } else if (a < 26) {
                         d.r[a - 19] = ST::dec(x);
-                    } else if constexpr (sizeof(typename ST::R) == 2) {
+                    } else if constexpr (REF_IN_PAIR) {
                         const C ref = ST::rdec(__builtin_bit_cast(typename ST::R, x));
                         if (a == 26) d.br = ref;
                         else d.bt = ref;
                     }
                 }
             }
-            if constexpr (sizeof(typename ST::R) != 2) {
+            if constexpr (!REF_IN_PAIR) {
                 d.br = n.br;
                 d.bt = n.bt;
             }
@@ -656,9 +670,12 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         if constexpr (PAIR) {
 #pragma unroll
             for (int p = 0; p < WORDS; ++p) n.w[p] = io.load_pair(p, row * NS, zoff * NS);
-            if constexpr (sizeof(typename ST::R) != 2) {
+            if constexpr (DEV && !REF_IN_PAIR) {
                 n.br = ST::rdec(io.load_ref(0, row * RSZ, zoff * RSZ));
                 n.bt = ST::rdec(io.load_ref(1, row * RSZ, zoff * RSZ));
+            } else if constexpr (!DEV) {
+                n.br = C(0);
+                n.bt = C(0);
             }
         } else {
 #pragma unroll
@@ -972,10 +989,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
             stored = true;
             // f_a and g_a of the same velocity (a = 0..6) go to the same
             // neighbour and share a word of the paired layout: one store.
-            auto word = [](E lo, E hi) -> unsigned {
-                return (unsigned)__builtin_bit_cast(unsigned short, lo) |
-                       ((unsigned)__builtin_bit_cast(unsigned short, hi) << 16);
-            };
+            auto word = [](E lo, E hi) { return pack_pair<E>(lo, hi); };
 #pragma unroll
             for (int a = 0; a < 7; ++a) {
                 const int ex = kE19X[a], ey = kE19Y[a], ez = kE19Z[a];
@@ -988,10 +1002,10 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
                 const int ex = kE19X[a], ey = kE19Y[a], ez = kE19Z[a];
                 io.store(a, Yo[ey + 1] + Xo[ex + 1], Zo[ez + 1], fval(a, sl[ez + 1], ex, ey));
             }
-            if constexpr (sizeof(typename ST::R) == 2) {
+            if constexpr (REF_IN_PAIR) {
                 io.store_pair(kPairOf[kPopPlanes], rowb, Zc,
                               word(__builtin_bit_cast(E, ST::renc(rho)), __builtin_bit_cast(E, ST::renc(T))));
-            } else {
+            } else if constexpr (DEV) {
                 io.store_ref(0, irow * RU, (unsigned)z * plane * RU, ST::renc(rho));
                 io.store_ref(1, irow * RU, (unsigned)z * plane * RU, ST::renc(T));
             }
