@@ -105,6 +105,11 @@ typedef struct lbm_params {
                              /* bc_z = LBM_BC_PERIODIC and thermal = 1.  The   */
                              /* density lattice stays periodic.                */
     double T_shell;          /* reservoir temperature, > 0 when bc_T_shell     */
+    int thermal_bgk;         /* 0: MRT temperature collision, Eqs. (37)-(43);  */
+                             /* 1: BGK, Eq. (19): one relaxation time          */
+                             /* tau_g = 1/2 + chi/c_sT^2 for every moment (the */
+                             /* MRT one with varsigma_q = varsigma_pi = tau_g),*/
+                             /* grad T from Eq. (36)                           */
 } lbm_params;
 
 typedef struct lbm_handle lbm_handle;

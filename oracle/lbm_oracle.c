@@ -52,6 +52,7 @@ typedef struct orc_params {
     int thermal;           /* 1: temperature lattice evolves; 0: held fixed */
     int bc_T_shell;        /* 1: outer layer of nodes held at T_shell (Sec. IV A) */
     double T_shell;        /* temperature of that layer */
+    int thermal_bgk;       /* 1: BGK temperature collision of Eq. (19) instead of the MRT one */
 } orc_params;
 
 typedef struct orc_sim {
@@ -460,7 +461,12 @@ static void pass_collide(orc_sim *s) {
         const double phis = adv - T / rhocV * dpdT * divu;
 
         /* Eq. (39) with Gamma of Eq. (43). */
-        const double Gam[Q7] = {1.0, 1.0 / vsT, 1.0 / vsT, 1.0 / vsT, 1.0 / p->vs_q, 1.0 / p->vs_pi, 1.0 / p->vs_pi};
+        double Gam[Q7] = {1.0, 1.0 / vsT, 1.0 / vsT, 1.0 / vsT, 1.0 / p->vs_q, 1.0 / p->vs_pi, 1.0 / p->vs_pi};
+        if (p->thermal_bgk) {
+            /* Eq. (19): g <- g - (g - w T)/tau_g + Q with tau_g = varsigma_T; in
+             * moment space every non-conserved moment relaxes at 1/tau_g. */
+            for (int k = 1; k < Q7; ++k) Gam[k] = 1.0 / vsT;
+        }
         for (int k = 0; k < Q7; ++k) ns[k] = n[k] - Gam[k] * (n[k] - neq[k]);
         /* Eqs. (23)-(24) with C_alpha = w_alpha phi_s, and Eq. (40). */
         for (int a = 0; a < Q7; ++a) {
@@ -565,6 +571,7 @@ int orc_create(const orc_params *p, orc_sim **out) {
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return ORC_EINVAL;
     if (p->bc_z != 0 && p->nz < 3) return ORC_EINVAL;
     if (p->bc_T_shell && (p->bc_z != 0 || !p->thermal || !(p->T_shell > 0.0))) return ORC_EINVAL;
+    if (p->thermal_bgk != 0 && p->thermal_bgk != 1) return ORC_EINVAL;
     if (p->tau_e <= 0.5 || p->tau_v <= 0.5 || p->tau_q <= 0.5 || p->tau_pi <= 0.5) return ORC_EINVAL;
     if (p->vs_q <= 0.5 || p->vs_pi <= 0.5 || p->G == 0.0 || p->cV <= 0.0) return ORC_EINVAL;
     orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));

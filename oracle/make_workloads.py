@@ -34,7 +34,7 @@ A_IVA, A_IVC, B, R, OMEGA = 1.0 / 49.0, 2.0 / 49.0, 2.0 / 21.0, 1.0, 0.344
 BASE = dict(a=A_IVA, b=B, R=R, acentric=OMEGA, G=-1.0, tau_e=1.25, tau_v=0.8, tau_q=1.0, tau_pi=1.0,
             cV=5.0, d=0.95, kappa_mode=0, kappa=0.2, vs_q=1.0, vs_pi=1.0, grav=[0.0, 0.0, 0.0],
             T_wall_patch=0.0, T_wall=0.0, patch_radius=0.0, T_top=0.0, thermal=1, bc_z=0, bc_T_shell=0,
-            T_shell=0.0)
+            T_shell=0.0, thermal_bgk=0)
 # Reading: tanh profiles use rho = (l+g)/2 - (l-g)/2 tanh(2 (r-R)/W) with W = 4;
 # W = 2 starts the coupled thermal run with a transient that makes it diverge.
 WIDTH = 4.0

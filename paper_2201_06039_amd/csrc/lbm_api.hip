@@ -65,6 +65,7 @@ bool valid_params(const lbm_params *p) {
     if (p->a < 0.0 || p->b < 0.0 || p->R < 0.0) return false;
     if (p->thermal != 0 && p->thermal != 1) return false;
     if (p->bc_T_shell != 0 && p->bc_T_shell != 1) return false;
+    if (p->thermal_bgk != 0 && p->thermal_bgk != 1) return false;
     if (p->bc_T_shell && (p->bc_z != LBM_BC_PERIODIC || !p->thermal || !(p->T_shell > 0.0))) return false;
     return true;
 }
@@ -167,6 +168,7 @@ lbm::Phys<C> make_phys(const lbm_params *p) {
     P.kappa_mode = p->kappa_mode;
     P.thermal = p->thermal;
     P.shell = p->bc_T_shell;
+    P.thermal_bgk = p->thermal_bgk;
     P.T_shell = (C)p->T_shell;
     P.attract = p->a != 0.0;
     P.gravity = (p->g[0] != 0.0 || p->g[1] != 0.0 || p->g[2] != 0.0);

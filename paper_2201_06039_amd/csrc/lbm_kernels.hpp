@@ -80,6 +80,7 @@ struct Phys {
     int kappa_mode;       // 0: constant lambda, 1: constant chi
     int thermal;          // temperature lattice evolves
     int shell;            // outer layer of nodes held at T_shell (periodic grids only)
+    int thermal_bgk;      // single relaxation time for the temperature lattice, Eq. (19)
     C T_shell;
     int attract;          // a != 0
     int gravity;          // g != 0
@@ -897,8 +898,10 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
             // n4 - d T = (1 - d) T - g0 = w0 (T - T_r) - (g0 - w0 T_r).
             const C keep = C(1) - inv_vsT;
             const C s1 = n1 * keep, s2 = n2 * keep, s3 = n3 * keep;
-            const C s4 = fmad(K * P.wT0, T - nd.bt, -nd.r[0]) * (C(1) - P.gam_q);
-            const C s5 = n5 * (C(1) - P.gam_pi), s6 = n6 * (C(1) - P.gam_pi);
+            // The BGK collision of Eq. (19) is the MRT one with every rate 1/tau_g = 1/varsigma_T.
+            const C gq = P.thermal_bgk ? inv_vsT : P.gam_q, gp = P.thermal_bgk ? inv_vsT : P.gam_pi;
+            const C s4 = fmad(K * P.wT0, T - nd.bt, -nd.r[0]) * (C(1) - gq);
+            const C s5 = n5 * (C(1) - gp), s6 = n6 * (C(1) - gp);
             // Eqs. (23)-(24): Q = w (1.5 phi_s - 0.5 phi_s(t-1))
             C *phi_own = A.phi + own;
             const C qs = fmad(C(1.5), phis, C(-0.5) * *phi_own);

@@ -34,7 +34,7 @@ class LbmParams(ctypes.Structure):
         ("T_wall_patch", ctypes.c_double), ("T_wall", ctypes.c_double),
         ("patch_radius", ctypes.c_double), ("T_top", ctypes.c_double),
         ("thermal", ctypes.c_int), ("storage", ctypes.c_int),
-        ("bc_T_shell", ctypes.c_int), ("T_shell", ctypes.c_double),
+        ("bc_T_shell", ctypes.c_int), ("T_shell", ctypes.c_double), ("thermal_bgk", ctypes.c_int),
     ]
 
 
@@ -120,6 +120,7 @@ def make_params(params: dict, storage="f32") -> LbmParams:
     src.setdefault("storage", _STORAGE_NAMES[storage] if isinstance(storage, str) else storage)
     src.setdefault("bc_T_shell", 0)
     src.setdefault("T_shell", 0.0)
+    src.setdefault("thermal_bgk", 0)
     for n in names:
         if n not in src:
             raise KeyError(f"missing parameter {n!r}")

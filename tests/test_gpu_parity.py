@@ -206,3 +206,20 @@ def test_deviation_storage_launch_shape_bitwise(storage):
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
             assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_thermal_bgk_collision(storage):
+    """The BGK temperature collision of Eq. (19) (constant lambda, so tau_g
+    varies with rho per node), evaporation 40^3 with noise."""
+    w = workload("evaporation_128", nx=40, ny=40, nz=40, radius=9.0, thermal_bgk=1)
+    _say(f"thermal BGK {storage}")
+    ref = run_oracle(w, 60)
+    e = errors(run_gpu(w, 60, storage), ref)
+    _say(f"  errors {e}")
+    if storage == "f64":
+        _check(e, FP64_TOL)
+    elif storage == "f32":
+        _check(e, FP32_TOL, tol_u=fp32_u_tol(60, ref))
+    else:
+        assert e["rho"] <= DEV_TOL["f16"] and e["T"] <= DEV_TOL["f16"] and e["u_l2"] <= 20 * DEV_TOL["f16"], e

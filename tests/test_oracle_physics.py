@@ -198,6 +198,59 @@ def test_thermal_diffusivity_d3q7(oracle_lib):
         assert _decay_rate(ts[2:], amps[2:]) / k ** 2 == pytest.approx(chi, rel=5e-3)
 
 
+def test_thermal_bgk_collision_in_population_space(oracle_lib):
+    """Eq. (19): with the BGK temperature collision every population relaxes
+    towards w_alpha T at the single rate 1/tau_g, tau_g = 1/2 + chi/c_sT^2.
+    On a uniform grid with no source (a = b = R = 0, u = 0) streaming leaves a
+    uniform state unchanged, so one step maps g to g - (g - w T)/tau_g exactly;
+    the MRT collision with varsigma_q = varsigma_pi = 1 does not (it relaxes
+    n_4..n_6 at rate 1)."""
+    n = 4
+    chi, d = 0.05, 0.95
+    csT2 = d / 3.0
+    tau = 0.5 + chi / csT2
+    w = np.array([1.0 - d] + [d / 6.0] * 6)
+    T = 1.3
+    delta = np.array([0.02, -0.013, 0.007, 0.011, -0.004, 0.009, -0.03])
+    g0 = w * T + delta
+    ones = np.ones((n, n, n))
+    outs = {}
+    for bgk in (1, 0):
+        s = oracle_lib.Sim(nx=n, ny=n, nz=n, a=0.0, b=0.0, R=0.0, kappa_mode=1, kappa=chi, thermal_bgk=bgk)
+        s.init_fields(ones, 0 * ones, 0 * ones, 0 * ones, T * ones)
+        st = s.state()
+        g = np.broadcast_to(g0[:, None, None, None], st["g"].shape).copy()
+        s.set_state(st["f"], g, st["phi_prev"], st["rho_ave"])
+        s.step(1)
+        outs[bgk] = s.state()["g"][:, 1, 2, 3]
+        s.close()
+    Tn = g0.sum()
+    expect = g0 - (g0 - w * Tn) / tau
+    np.testing.assert_allclose(outs[1], expect, rtol=0, atol=1e-15)
+    assert np.abs(outs[0] - expect).max() > 1e-4
+
+
+def test_thermal_bgk_diffusivity(oracle_lib):
+    """Eq. (35) for the BGK version: a temperature mode decays at chi k^2 with
+    chi = (tau_g - 1/2) c_sT^2."""
+    L = 64
+    x = np.arange(L)
+    k = 2 * np.pi / L
+    for chi in (0.02, 0.3):
+        T = (1.0 + 1e-3 * np.sin(k * x)).reshape(1, 1, L)
+        ones = np.ones_like(T)
+        s = oracle_lib.Sim(nx=L, ny=1, nz=1, a=0.0, b=0.0, R=0.0, kappa_mode=1, kappa=chi, thermal_bgk=1)
+        s.init_fields(ones, 0 * ones, 0 * ones, 0 * ones, T)
+        ts, amps = [], []
+        for t in range(0, 600, 50):
+            if t:
+                s.step(50)
+            Tn = s.rho_u_T()[4].reshape(L)
+            ts.append(t)
+            amps.append(2.0 / L * ((Tn - 1.0) * np.sin(k * x)).sum())
+        assert _decay_rate(ts[2:], amps[2:]) / k ** 2 == pytest.approx(chi, rel=5e-3)
+
+
 def test_temperature_advected_by_source_term(oracle_lib):
     """g_eq = w T carries no velocity: convection enters only through the
     -u . grad T part of phi_s (Eq. 18) with the local gradient of Eq. (45) and
