@@ -5,7 +5,8 @@
  * EOS of Eq. (49)) coupled to a D3Q7 MRT temperature lattice (Sec. III C,
  * Eqs. (37)-(45)) whose phase-change source, Eq. (18), uses the local
  * temperature gradient of Eq. (45) and the local velocity divergence of
- * Eq. (48).
+ * Eq. (48).  As an option the temperature lattice is D3Q19 with the BGK
+ * collision of Eq. (19) and the gradient of Eq. (36) (Sec. III B, Sec. V).
  *
  * THIS IS TEST INFRASTRUCTURE, NOT PRODUCT CODE.  Only the test suite, the
  * smoke check and the CPU-baseline leg of the benchmark may load it.  It
@@ -53,6 +54,7 @@ typedef struct orc_params {
     int bc_T_shell;        /* 1: outer layer of nodes held at T_shell (Sec. IV A) */
     double T_shell;        /* temperature of that layer */
     int thermal_bgk;       /* 1: BGK temperature collision of Eq. (19) instead of the MRT one */
+    int thermal_lattice;   /* 0: D3Q7 (Sec. III B); 1: D3Q19 with the standard weights, BGK only */
 } orc_params;
 
 typedef struct orc_sim {
@@ -61,7 +63,10 @@ typedef struct orc_sim {
     double M[Q19][Q19], Minv[Q19][Q19];
     double N[Q7][Q7], Ninv[Q7][Q7];
     double omega[Q19];   /* omega(|e_alpha|^2) of Eq. (7) */
-    double wT[Q7];       /* D3Q7 equilibrium weights, Sec. III B */
+    int QT;              /* velocities of the temperature lattice: 7 or 19 */
+    const int (*ET)[3];  /* their components */
+    double wT[Q19];      /* equilibrium weights of the temperature lattice, Eq. (22) */
+    double csT2;         /* c_sT^2: d/3 for D3Q7, 1/3 for D3Q19 */
     double Tc;           /* critical temperature implied by a, b, R */
     double *f, *g, *phi_prev;   /* state at time t (post-streaming) */
     double *fs, *gp;            /* post-collision f* and g+ */
@@ -170,9 +175,25 @@ static int build_tables(orc_sim *s) {
         const int e2 = E19[a][0] * E19[a][0] + E19[a][1] * E19[a][1] + E19[a][2] * E19[a][2];
         s->omega[a] = e2 == 1 ? 1.0 / 6.0 : (e2 == 2 ? 1.0 / 12.0 : 0.0);
     }
-    /* Sec. III B: w0 = 1 - d, w1..6 = d/6. */
-    s->wT[0] = 1.0 - s->p.d;
-    for (int a = 1; a < Q7; ++a) s->wT[a] = s->p.d / 6.0;
+    if (s->p.thermal_lattice == 0) {
+        /* Sec. III B, Eq. (22): w0 = 1 - d, w1..6 = d/6, c_sT^2 = d/3. */
+        s->QT = Q7;
+        s->ET = E7;
+        s->wT[0] = 1.0 - s->p.d;
+        for (int a = 1; a < Q7; ++a) s->wT[a] = s->p.d / 6.0;
+        s->csT2 = s->p.d / 3.0;
+    } else {
+        /* Sec. III B: on D3Q19 the weights are the standard ones, 1/3 at
+         * rest, 1/18 along the axes and 1/36 along the diagonals, and
+         * c_sT^2 = c_s^2 = 1/3. */
+        s->QT = Q19;
+        s->ET = E19;
+        for (int a = 0; a < Q19; ++a) {
+            const int e2 = E19[a][0] * E19[a][0] + E19[a][1] * E19[a][1] + E19[a][2] * E19[a][2];
+            s->wT[a] = e2 == 0 ? 1.0 / 3.0 : (e2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+        }
+        s->csT2 = 1.0 / 3.0;
+    }
     return ORC_OK;
 }
 
@@ -321,7 +342,7 @@ static void pass_macro(orc_sim *s) {
     for (long i = 0; i < nn; ++i) {
         double rho = 0.0, T = 0.0;
         for (int a = 0; a < Q19; ++a) rho += s->f[a * nn + i];
-        for (int a = 0; a < Q7; ++a) T += s->g[a * nn + i];
+        for (int a = 0; a < s->QT; ++a) T += s->g[a * nn + i];
         const double p2 = psi_squared(&s->p, s->Tc, rho, T);
         if (!(rho > 0.0) || !(p2 >= 0.0) || !(T == T)) bad = 1;
         s->rho[i] = rho;
@@ -388,7 +409,8 @@ static void pass_collide(orc_sim *s) {
     const orc_params *p = &s->p;
     const long nn = s->nn;
     const double cs2 = 1.0 / 3.0, dt = 1.0;
-    const double csT2 = p->d / 3.0;   /* Eq. (22): c_sT^2 = d/3 */
+    const double csT2 = s->csT2;      /* Eq. (22): c_sT^2 = d/3 (D3Q7) or 1/3 (D3Q19) */
+    const int QT = s->QT;
     double lam[Q19];
     relaxation_rates(p, lam);
 #pragma omp parallel for schedule(static)
@@ -420,7 +442,7 @@ static void pass_collide(orc_sim *s) {
         if (p->bc_T_shell) {
             const int x = (int)(i % p->nx), y = (int)((i / p->nx) % p->ny), z = (int)(i / ((long)p->nx * p->ny));
             if (in_shell(p, x, y, z)) {
-                for (int a = 0; a < Q7; ++a) s->gp[a * nn + i] = s->wT[a] * p->T_shell;
+                for (int a = 0; a < QT; ++a) s->gp[a * nn + i] = s->wT[a] * p->T_shell;
                 continue;
             }
         }
@@ -431,24 +453,32 @@ static void pass_collide(orc_sim *s) {
         const double divu = (-(m[4] - meq[4]) / (p->tau_e * dt) + (1.0 - 1.0 / (2.0 * p->tau_e)) * S[4] - 2.0 * Fu)
                             / (2.0 * rho * cs2);
 
-        /* Eq. (38): n = N g; Eq. (42): n_eq. */
-        double gl[Q7], n[Q7], neq[Q7], ns[Q7];
-        for (int a = 0; a < Q7; ++a) gl[a] = s->g[a * nn + i];
-        for (int k = 0; k < Q7; ++k) {
-            n[k] = 0.0;
-            for (int a = 0; a < Q7; ++a) n[k] += s->N[k][a] * gl[a];
-        }
         const double T = s->T[i];
-        neq[0] = T; neq[1] = 0.0; neq[2] = 0.0; neq[3] = 0.0;
-        neq[4] = 3.0 * csT2 * T; neq[5] = 0.0; neq[6] = 0.0;
-
         /* chi = lambda/(rho cV) (constant lambda) or given; chi = (vs_T - 0.5) c_sT^2 dt. */
         const double chi = p->kappa_mode == 0 ? p->kappa / (rho * p->cV) : p->kappa;
         const double vsT = 0.5 + chi / (csT2 * dt);
 
-        /* Eq. (45): local temperature gradient. */
-        double gradT[3];
-        for (int c = 0; c < 3; ++c) gradT[c] = -(n[1 + c] - neq[1 + c]) / (vsT * csT2 * dt);
+        double gl[Q19], gradT[3];
+        for (int a = 0; a < QT; ++a) gl[a] = s->g[a * nn + i];
+        double n[Q7], neq[Q7];
+        if (QT == Q7) {
+            /* Eq. (38): n = N g; Eq. (42): n_eq. */
+            for (int k = 0; k < Q7; ++k) {
+                n[k] = 0.0;
+                for (int a = 0; a < Q7; ++a) n[k] += s->N[k][a] * gl[a];
+            }
+            neq[0] = T; neq[1] = 0.0; neq[2] = 0.0; neq[3] = 0.0;
+            neq[4] = 3.0 * csT2 * T; neq[5] = 0.0; neq[6] = 0.0;
+            /* Eq. (45): local temperature gradient. */
+            for (int c = 0; c < 3; ++c) gradT[c] = -(n[1 + c] - neq[1 + c]) / (vsT * csT2 * dt);
+        } else {
+            /* Eq. (36): grad T = -sum e (g - w T) / (tau_g c_sT^2 dt), tau_g = vs_T. */
+            for (int c = 0; c < 3; ++c) {
+                double acc = 0.0;
+                for (int a = 0; a < Q19; ++a) acc += E19[a][c] * (gl[a] - s->wT[a] * T);
+                gradT[c] = -acc / (vsT * csT2 * dt);
+            }
+        }
 
         /* Eq. (18) with (dp/dT)_rho ~ rho R/(1 - b rho) (Sec. IV A); c_V constant. */
         const double rhocV = rho * p->cV;
@@ -460,27 +490,39 @@ static void pass_collide(orc_sim *s) {
         const double dpdT = rho * p->R / (1.0 - p->b * rho);
         const double phis = adv - T / rhocV * dpdT * divu;
 
-        /* Eq. (39) with Gamma of Eq. (43). */
-        double Gam[Q7] = {1.0, 1.0 / vsT, 1.0 / vsT, 1.0 / vsT, 1.0 / p->vs_q, 1.0 / p->vs_pi, 1.0 / p->vs_pi};
-        if (p->thermal_bgk) {
-            /* Eq. (19): g <- g - (g - w T)/tau_g + Q with tau_g = varsigma_T; in
-             * moment space every non-conserved moment relaxes at 1/tau_g. */
-            for (int k = 1; k < Q7; ++k) Gam[k] = 1.0 / vsT;
-        }
-        for (int k = 0; k < Q7; ++k) ns[k] = n[k] - Gam[k] * (n[k] - neq[k]);
-        /* Eqs. (23)-(24) with C_alpha = w_alpha phi_s, and Eq. (40). */
-        for (int a = 0; a < Q7; ++a) {
-            double acc = 0.0;
-            for (int k = 0; k < Q7; ++k) acc += s->Ninv[a][k] * ns[k];
-            const double Q = 1.5 * s->wT[a] * phis - 0.5 * s->wT[a] * s->phi_prev[i];
-            s->gp[a * nn + i] = acc + dt * Q;
+        if (QT == Q7) {
+            /* Eq. (39) with Gamma of Eq. (43). */
+            double ns[Q7];
+            double Gam[Q7] = {1.0, 1.0 / vsT, 1.0 / vsT, 1.0 / vsT, 1.0 / p->vs_q, 1.0 / p->vs_pi, 1.0 / p->vs_pi};
+            if (p->thermal_bgk) {
+                /* Eq. (19): g <- g - (g - w T)/tau_g + Q with tau_g = varsigma_T; in
+                 * moment space every non-conserved moment relaxes at 1/tau_g. */
+                for (int k = 1; k < Q7; ++k) Gam[k] = 1.0 / vsT;
+            }
+            for (int k = 0; k < Q7; ++k) ns[k] = n[k] - Gam[k] * (n[k] - neq[k]);
+            /* Eqs. (23)-(24) with C_alpha = w_alpha phi_s, and Eq. (40). */
+            for (int a = 0; a < Q7; ++a) {
+                double acc = 0.0;
+                for (int k = 0; k < Q7; ++k) acc += s->Ninv[a][k] * ns[k];
+                const double Q = 1.5 * s->wT[a] * phis - 0.5 * s->wT[a] * s->phi_prev[i];
+                s->gp[a * nn + i] = acc + dt * Q;
+            }
+        } else {
+            /* Eq. (19) in population space with g_eq = w T (Eq. (20)) and the
+             * source of Eqs. (23)-(24), C_alpha = w_alpha phi_s. */
+            for (int a = 0; a < Q19; ++a) {
+                const double geq = s->wT[a] * T;
+                const double Q = 1.5 * s->wT[a] * phis - 0.5 * s->wT[a] * s->phi_prev[i];
+                s->gp[a * nn + i] = gl[a] - (gl[a] - geq) / vsT + dt * Q;
+            }
         }
         s->phi_prev[i] = phis;
     }
 }
 
+/* The velocity opposite to e_a; the D3Q7 velocities are the first seven of
+ * D3Q19 in the same order, so one rule serves both lattices. */
 static int opposite19(int a) { return a == 0 ? 0 : ((a & 1) ? a + 1 : a - 1); }
-static int opposite7(int a) { return a == 0 ? 0 : ((a & 1) ? a + 1 : a - 1); }
 
 /* Eq. (4) and Eq. (40): f(x + e, t + 1) = f*(x, t), g(x + e, t + 1) = g+(x, t),
  * periodic in x and y.  With walls: Eq. (50) halfway bounce-back of f and
@@ -511,18 +553,18 @@ static void pass_stream(orc_sim *s) {
                     s->fn[a * nn + node_index(p, xd, yd, zd)] = s->fs[a * nn + i];
                 }
                 if (!p->thermal) continue;
-                for (int a = 0; a < Q7; ++a) {
-                    const int xd = ((x + E7[a][0]) % p->nx + p->nx) % p->nx;
-                    const int yd = ((y + E7[a][1]) % p->ny + p->ny) % p->ny;
-                    int zd = z + E7[a][2];
+                for (int a = 0; a < s->QT; ++a) {
+                    const int xd = ((x + s->ET[a][0]) % p->nx + p->nx) % p->nx;
+                    const int yd = ((y + s->ET[a][1]) % p->ny + p->ny) % p->ny;
+                    int zd = z + s->ET[a][2];
                     if (!walls) {
                         zd = (zd % p->nz + p->nz) % p->nz;
                     } else if (zd < 0) {
                         const double Tw = bottom_wall_temperature(p, x, y);
-                        s->gn[opposite7(a) * nn + i] = -s->gp[a * nn + i] + 2.0 * s->wT[a] * Tw;
+                        s->gn[opposite19(a) * nn + i] = -s->gp[a * nn + i] + 2.0 * s->wT[a] * Tw;
                         continue;
                     } else if (zd > p->nz - 1) {
-                        s->gn[opposite7(a) * nn + i] = -s->gp[a * nn + i] + 2.0 * s->wT[a] * p->T_top;
+                        s->gn[opposite19(a) * nn + i] = -s->gp[a * nn + i] + 2.0 * s->wT[a] * p->T_top;
                         continue;
                     }
                     s->gn[a * nn + node_index(p, xd, yd, zd)] = s->gp[a * nn + i];
@@ -533,7 +575,7 @@ static void pass_stream(orc_sim *s) {
             for (int y = 0; y < p->ny; ++y)
                 for (int x = 0; x < p->nx; ++x)
                     if (in_shell(p, x, y, z))
-                        for (int a = 0; a < Q7; ++a) s->gn[a * nn + node_index(p, x, y, z)] = s->wT[a] * p->T_shell;
+                        for (int a = 0; a < s->QT; ++a) s->gn[a * nn + node_index(p, x, y, z)] = s->wT[a] * p->T_shell;
     }
     if (walls) {
         const int zt = p->nz - 1;
@@ -572,6 +614,9 @@ int orc_create(const orc_params *p, orc_sim **out) {
     if (p->bc_z != 0 && p->nz < 3) return ORC_EINVAL;
     if (p->bc_T_shell && (p->bc_z != 0 || !p->thermal || !(p->T_shell > 0.0))) return ORC_EINVAL;
     if (p->thermal_bgk != 0 && p->thermal_bgk != 1) return ORC_EINVAL;
+    /* Reading: the paper gives relaxation rates for the D3Q7 moments only,
+     * so the D3Q19 temperature lattice takes the BGK collision. */
+    if (p->thermal_lattice != 0 && (p->thermal_lattice != 1 || !p->thermal_bgk)) return ORC_EINVAL;
     if (p->tau_e <= 0.5 || p->tau_v <= 0.5 || p->tau_q <= 0.5 || p->tau_pi <= 0.5) return ORC_EINVAL;
     if (p->vs_q <= 0.5 || p->vs_pi <= 0.5 || p->G == 0.0 || p->cV <= 0.0) return ORC_EINVAL;
     orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
@@ -583,9 +628,9 @@ int orc_create(const orc_params *p, orc_sim **out) {
     s->f = calloc(Q19 * nn, sizeof(double));
     s->fs = calloc(Q19 * nn, sizeof(double));
     s->fn = calloc(Q19 * nn, sizeof(double));
-    s->g = calloc(Q7 * nn, sizeof(double));
-    s->gp = calloc(Q7 * nn, sizeof(double));
-    s->gn = calloc(Q7 * nn, sizeof(double));
+    s->g = calloc(Q19 * nn, sizeof(double));
+    s->gp = calloc(Q19 * nn, sizeof(double));
+    s->gn = calloc(Q19 * nn, sizeof(double));
     s->phi_prev = calloc(nn, sizeof(double));
     s->rho = calloc(nn, sizeof(double));
     s->T = calloc(nn, sizeof(double));
@@ -621,7 +666,7 @@ int orc_init_fields(orc_sim *s, const double *rho, const double *ux, const doubl
             for (int k = 0; k < Q19; ++k) acc += s->Minv[a][k] * meq[k];
             s->f[a * nn + i] = acc;
         }
-        for (int a = 0; a < Q7; ++a) s->g[a * nn + i] = s->wT[a] * T[i];
+        for (int a = 0; a < s->QT; ++a) s->g[a * nn + i] = s->wT[a] * T[i];
         s->phi_prev[i] = 0.0;
     }
     s->status = ORC_OK;
@@ -665,17 +710,17 @@ int orc_get_rho_u_T(orc_sim *s, double *rho, double *ux, double *uy, double *uz,
     return s->status;
 }
 
-/* Raw state: f (19 x nn), g (7 x nn), phi_s history (nn), average density. */
+/* Raw state: f (19 x nn), g (7 or 19 x nn), phi_s history (nn), average density. */
 void orc_get_state(const orc_sim *s, double *f, double *g, double *phi_prev, double *rho_ave) {
     memcpy(f, s->f, sizeof(double) * Q19 * s->nn);
-    memcpy(g, s->g, sizeof(double) * Q7 * s->nn);
+    memcpy(g, s->g, sizeof(double) * s->QT * s->nn);
     memcpy(phi_prev, s->phi_prev, sizeof(double) * s->nn);
     *rho_ave = s->rho_ave;
 }
 
 void orc_set_state(orc_sim *s, const double *f, const double *g, const double *phi_prev, double rho_ave) {
     memcpy(s->f, f, sizeof(double) * Q19 * s->nn);
-    memcpy(s->g, g, sizeof(double) * Q7 * s->nn);
+    memcpy(s->g, g, sizeof(double) * s->QT * s->nn);
     memcpy(s->phi_prev, phi_prev, sizeof(double) * s->nn);
     s->rho_ave = rho_ave;
     s->status = ORC_OK;
@@ -705,7 +750,7 @@ void orc_tables(const orc_params *p, double *M, double *Minv, double *N, double 
     memcpy(e19, E19, sizeof(E19));
     memcpy(e7, E7, sizeof(E7));
     memcpy(omega, s.omega, sizeof(s.omega));
-    memcpy(wT, s.wT, sizeof(s.wT));
+    memcpy(wT, s.wT, sizeof(double) * s.QT);
 }
 
 double orc_critical_temperature(const orc_params *p) { return critical_temperature(p); }

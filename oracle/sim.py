@@ -24,6 +24,7 @@ _PARAM_FIELDS = [
     ("T_wall_patch", ctypes.c_double), ("T_wall", ctypes.c_double),
     ("patch_radius", ctypes.c_double), ("T_top", ctypes.c_double), ("thermal", ctypes.c_int),
     ("bc_T_shell", ctypes.c_int), ("T_shell", ctypes.c_double), ("thermal_bgk", ctypes.c_int),
+    ("thermal_lattice", ctypes.c_int),
 ]
 
 
@@ -37,7 +38,7 @@ DEFAULTS = dict(nx=8, ny=8, nz=8, bc_z=0, a=2.0 / 49.0, b=2.0 / 21.0, R=1.0, ace
                 G=-1.0, sigma=0.0, tau_e=1.25, tau_v=0.8, tau_q=1.0, tau_pi=1.0, cV=5.0, d=0.95,
                 kappa_mode=0, kappa=0.2, vs_q=1.0, vs_pi=1.0, grav=(0.0, 0.0, 0.0),
                 T_wall_patch=0.0, T_wall=0.0, patch_radius=0.0, T_top=0.0, thermal=1, bc_T_shell=0, T_shell=0.0,
-                thermal_bgk=0)
+                thermal_bgk=0, thermal_lattice=0)
 
 _lib = None
 
@@ -120,6 +121,7 @@ class Sim:
         self._p = make_params(**params)
         self.shape = (self._p.nz, self._p.ny, self._p.nx)
         self.nn = self._p.nx * self._p.ny * self._p.nz
+        self.qt = Q19 if self._p.thermal_lattice else Q7  # velocities of the temperature lattice
         h = ctypes.c_void_p()
         rc = lib().orc_create(ctypes.byref(self._p), ctypes.byref(h))
         if rc != 0:
@@ -155,16 +157,16 @@ class Sim:
 
     def state(self):
         f = np.empty(Q19 * self.nn)
-        g = np.empty(Q7 * self.nn)
+        g = np.empty(self.qt * self.nn)
         ph = np.empty(self.nn)
         ra = np.empty(1)
         lib().orc_get_state(self._h, _dp(f), _dp(g), _dp(ph), _dp(ra))
-        return dict(f=f.reshape((Q19,) + self.shape), g=g.reshape((Q7,) + self.shape),
+        return dict(f=f.reshape((Q19,) + self.shape), g=g.reshape((self.qt,) + self.shape),
                     phi_prev=ph.reshape(self.shape), rho_ave=float(ra[0]))
 
     def set_state(self, f, g, phi_prev, rho_ave):
         f = _c64(f, Q19 * self.nn)
-        g = _c64(g, Q7 * self.nn)
+        g = _c64(g, self.qt * self.nn)
         ph = _c64(phi_prev, self.nn)
         lib().orc_set_state(self._h, _dp(f), _dp(g), _dp(ph), float(rho_ave))
 
@@ -185,9 +187,10 @@ def tables(**params):
     M = np.empty((Q19, Q19)); Minv = np.empty((Q19, Q19))
     N = np.empty((Q7, Q7)); Ninv = np.empty((Q7, Q7))
     e19 = np.empty((Q19, 3), dtype=np.int32); e7 = np.empty((Q7, 3), dtype=np.int32)
-    om = np.empty(Q19); wT = np.empty(Q7)
+    om = np.empty(Q19); wT = np.empty(Q19)
     ip = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
     lib().orc_tables(ctypes.byref(p), _dp(M), _dp(Minv), _dp(N), _dp(Ninv), ip(e19), ip(e7), _dp(om), _dp(wT))
+    wT = wT[:Q19 if p.thermal_lattice else Q7]
     return dict(M=M, Minv=Minv, N=N, Ninv=Ninv, e19=e19, e7=e7, omega=om, wT=wT)
 
 

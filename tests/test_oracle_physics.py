@@ -464,3 +464,190 @@ def test_checkpoint_continuation_is_bitwise(oracle_lib):
     for key in ("f", "g", "phi_prev"):
         assert np.array_equal(sa[key], sb[key])
     assert sa["rho_ave"] == sb["rho_ave"]
+
+
+# --------------------------------------------------------------------------
+# D3Q19 temperature lattice (Sec. III B: standard D3Q19 weights, c_sT^2 = 1/3,
+# BGK collision of Eq. (19) with the local gradient of Eq. (36))
+# --------------------------------------------------------------------------
+
+Q19T = dict(thermal_lattice=1, thermal_bgk=1)
+
+
+def test_d3q19_temperature_weights_satisfy_eq22(oracle_lib):
+    """sum w = 1, sum w e = 0 and sum w e e = c_sT^2 I with c_sT^2 = 1/3,
+    and the fourth-order isotropy of the standard weights (a wrong diagonal
+    weight keeps the first three and breaks the last)."""
+    t = oracle_lib.tables(**Q19T)
+    w, e = t["wT"], t["e19"].astype(float)
+    assert w.shape == (19,)
+    assert w.sum() == pytest.approx(1.0, abs=1e-15)
+    np.testing.assert_allclose(w @ e, 0.0, atol=1e-15)
+    np.testing.assert_allclose((w[:, None, None] * e[:, :, None] * e[:, None, :]).sum(0), np.eye(3) / 3.0, atol=1e-15)
+    xxxx = (w * e[:, 0] ** 4).sum()
+    xxyy = (w * e[:, 0] ** 2 * e[:, 1] ** 2).sum()
+    assert xxxx == pytest.approx(1.0 / 3.0, abs=1e-15) and xxyy == pytest.approx(1.0 / 9.0, abs=1e-15)
+    with pytest.raises(oracle_lib.OracleError):
+        oracle_lib.Sim(thermal_lattice=1, thermal_bgk=0)
+
+
+def test_d3q19_temperature_bgk_one_step(oracle_lib):
+    """Eq. (19) on D3Q19: a uniform grid with no source maps g to
+    g - (g - w T)/tau_g in one step, tau_g = 1/2 + chi/c_sT^2 with c_sT^2 = 1/3
+    (with the D3Q7 value d/3 tau_g would be 5 % off)."""
+    n = 3
+    chi = 0.05
+    tau = 0.5 + 3.0 * chi
+    w = oracle_lib.tables(**Q19T)["wT"]
+    rng = np.random.default_rng(5)
+    T = 1.3
+    g0 = w * T + 0.01 * rng.standard_normal(19)
+    ones = np.ones((n, n, n))
+    s = oracle_lib.Sim(nx=n, ny=n, nz=n, a=0.0, b=0.0, R=0.0, kappa_mode=1, kappa=chi, **Q19T)
+    s.init_fields(ones, 0 * ones, 0 * ones, 0 * ones, T * ones)
+    st = s.state()
+    assert st["g"].shape == (19, n, n, n)
+    g = np.broadcast_to(g0[:, None, None, None], st["g"].shape).copy()
+    s.set_state(st["f"], g, st["phi_prev"], st["rho_ave"])
+    s.step(1)
+    got = s.state()["g"][:, 1, 2, 0]
+    np.testing.assert_allclose(got, g0 - (g0 - w * g0.sum()) / tau, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("direction", ["axis", "diagonal"])
+def test_d3q19_temperature_diffusivity(oracle_lib, direction):
+    """Eq. (35): a temperature mode decays at chi k^2, chi = (tau_g - 1/2)/3,
+    along an axis and along a face diagonal (isotropy of the weights)."""
+    L = 64
+    k = 2 * np.pi / L
+    x = np.arange(L)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    phase = k * (X if direction == "axis" else X + Y)
+    kk = k * k * (1 if direction == "axis" else 2)
+    mode = np.sin(phase).reshape(1, L, L)
+    for chi in (0.02, 0.2):
+        ones = np.ones_like(mode)
+        s = oracle_lib.Sim(nx=L, ny=L, nz=1, a=0.0, b=0.0, R=0.0, kappa_mode=1, kappa=chi, **Q19T)
+        s.init_fields(ones, 0 * ones, 0 * ones, 0 * ones, 1.0 + 1e-3 * mode)
+        ts, amps = [], []
+        for t in range(0, 600, 60):
+            if t:
+                s.step(60)
+            Tn = s.rho_u_T()[4]
+            ts.append(t)
+            amps.append(((Tn - 1.0) * mode).sum() / (mode * mode).sum())
+        assert _decay_rate(ts[2:], amps[2:]) / kk == pytest.approx(chi, rel=5e-3)
+
+
+def test_d3q19_temperature_advected_by_source_term(oracle_lib):
+    """Eq. (36) gives the gradient in -u . grad T: a wave in a uniform flow
+    travels at u and decays at chi k^2 (a wrong scale of the gradient changes
+    the speed, a wrong sign reverses it)."""
+    L = 64
+    x = np.arange(L)
+    k = 2 * np.pi / L
+    u0, chi, steps = 0.02, 0.05, 400
+    T = (1.0 + 1e-3 * np.sin(k * x)).reshape(1, 1, L)
+    ones = np.ones_like(T)
+    s = oracle_lib.Sim(nx=L, ny=1, nz=1, a=0.0, b=0.0, R=0.0, kappa_mode=1, kappa=chi, **Q19T)
+    s.init_fields(ones, u0 * ones, 0 * ones, 0 * ones, T)
+    c0 = ((T.reshape(L) - 1.0) * np.exp(-1j * k * x)).sum()
+    s.step(steps)
+    Tn = s.rho_u_T()[4].reshape(L)
+    c1 = ((Tn - 1.0) * np.exp(-1j * k * x)).sum()
+    assert -np.angle(c1 / c0) / k == pytest.approx(u0 * steps, rel=2e-2)
+    assert abs(c1) / abs(c0) == pytest.approx(np.exp(-chi * k * k * steps), rel=2e-2)
+
+
+def test_d3q19_temperature_compression_heating(oracle_lib):
+    """The div u term of Eq. (18) on the D3Q19 temperature lattice:
+    dT = T R/(rho c_V (1 - b rho)) d rho."""
+    L = 64
+    x = np.arange(L)
+    T0, rho0, cV, Rg = 0.1, 1.0, 5.0, 1.0
+    rho = (rho0 + 1e-3 * np.sin(2 * np.pi * x / L)).reshape(1, 1, L)
+    ones = np.ones_like(rho)
+    s = oracle_lib.Sim(nx=L, ny=1, nz=1, a=0.0, b=0.0, R=Rg, cV=cV, kappa_mode=1, kappa=0.001, **Q19T)
+    s.init_fields(rho, 0 * ones, 0 * ones, 0 * ones, T0 * ones)
+    r0 = s.rho_u_T()[0].reshape(L).copy()
+    s.step(100)
+    r, _, _, _, T = s.rho_u_T()
+    dr = r.reshape(L) - r0
+    dT = T.reshape(L) - T0
+    assert (dr * dT).sum() / (dr * dr).sum() == pytest.approx(T0 * Rg / (rho0 * cV), rel=2e-2)
+
+
+def test_d3q19_temperature_wall_conduction_profile(oracle_lib):
+    """Eq. (51) with the D3Q19 weights (five links cross each wall): the
+    steady profile is linear between z = -1/2 and z = nz - 1/2."""
+    nz = 16
+    ones = np.ones((nz, 2, 3))
+    Tw, Tt = 1.1, 1.0
+    s = oracle_lib.Sim(nx=3, ny=2, nz=nz, bc_z=1, a=0.0, b=0.0, R=0.0, kappa_mode=1, kappa=0.1,
+                       T_wall_patch=Tw, T_wall=Tw, T_top=Tt, patch_radius=0.0, **Q19T)
+    s.init_fields(ones, 0 * ones, 0 * ones, 0 * ones, Tt * ones)
+    s.step(20000)
+    T = s.rho_u_T()[4]
+    assert np.abs(T - T[:, :1, :1]).max() < 1e-13
+    z = np.arange(nz)
+    expect = Tw + (Tt - Tw) * (z + 0.5) / nz
+    np.testing.assert_allclose((T[:, 0, 0] - Tt) / (Tw - Tt), (expect - Tt) / (Tw - Tt), atol=2e-3)
+
+
+def test_d3q19_temperature_uniform_fixed_point_with_walls(oracle_lib):
+    Tc, T, rl, rg = coexistence()
+    nx, ny, nz = 5, 4, 7
+    s = oracle_lib.Sim(nx=nx, ny=ny, nz=nz, bc_z=1, sigma=0.11, kappa_mode=1, kappa=0.08,
+                       grav=(0, 0, -2e-5), T_wall_patch=T, T_wall=T, T_top=T, patch_radius=1.5, **Q19T)
+    ones = np.ones((nz, ny, nx))
+    s.init_fields(6.0 * ones, 0 * ones, 0 * ones, 0 * ones, T * ones)
+    st0 = s.state()
+    s.step(20)
+    st1 = s.state()
+    np.testing.assert_allclose(st1["f"], st0["f"], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(st1["g"], st0["g"], rtol=0, atol=1e-16)
+
+
+def test_d3q19_temperature_budget_and_reservoir(oracle_lib):
+    """sum T(t+1) - sum T(t) = sum Q on a periodic grid (Eqs. 23-24), and the
+    reservoir layer stays at T_shell exactly."""
+    s = droplet_sim(oracle_lib, noise=1e-3, **Q19T)
+    s.step(3)
+    for _ in range(5):
+        _, E0 = s.reduce()
+        ph0 = s.state()["phi_prev"]
+        s.step(1)
+        _, E1 = s.reduce()
+        ph1 = s.state()["phi_prev"]
+        expect = (1.5 * ph1 - 0.5 * ph0).sum()
+        assert abs((E1 - E0) - expect) < 1e-13 * E0
+    assert abs(expect) > 0
+    Tc, T, rl, rg = coexistence()
+    r = droplet_sim(oracle_lib, n=12, radius=3.5, bc_T_shell=1, T_shell=1.02 * T, **Q19T)
+    r.step(30)
+    Tn = r.rho_u_T()[4]
+    for face in (Tn[0], Tn[-1], Tn[:, 0], Tn[:, -1], Tn[:, :, 0], Tn[:, :, -1]):
+        assert np.abs(face - 1.02 * T).max() <= 1e-15
+
+
+def test_d3q7_and_d3q19_temperature_lattices_agree(oracle_lib):
+    """Both lattices solve Eqs. (17)-(18) (Sec. III B): an evaporating droplet
+    (vapour 0.05 Tc hotter, constant chi) evolves the same on either, up to
+    the discretisation error -- the temperature change they produce agrees to
+    a few per cent, while the change itself is of order the superheat."""
+    Tc, T, rl, rg = coexistence()
+    n = 20
+    W = workloads()
+    fields = W.droplet(n, n, n, 5.0, rl, rg, T, T + 0.05 * Tc, width=4.0, noise=0.0, seed=1)
+    out = {}
+    for name, kw in (("q7", dict(thermal_bgk=1)), ("q19", Q19T)):
+        s = oracle_lib.Sim(nx=n, ny=n, nz=n, sigma=sigma_default(), kappa_mode=1, kappa=0.05, **kw)
+        s.init_fields(*fields)
+        s.step(200)
+        out[name] = s.rho_u_T()
+    dT7 = out["q7"][4] - fields[4]
+    dT19 = out["q19"][4] - fields[4]
+    scale = np.abs(dT7).max()
+    assert scale > 0.02 * Tc
+    assert np.abs(dT19 - dT7).max() < 0.05 * scale
+    assert np.abs(out["q19"][0] - out["q7"][0]).max() < 1e-2 * rl
