@@ -2,7 +2,8 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                     [--storage f16|f32|f64|bf16|f32dev] [--compare f32|none]
-                    [--tile TXxTY] [--chunk CZ] [--no-precision] [--no-batch] [--no-cpu-baseline]
+                    [--thermal-lattice d3q7|d3q19] [--tile TXxTY] [--chunk CZ]
+                    [--no-precision] [--no-batch] [--no-lattice-comparison] [--no-cpu-baseline]
 
 One step = one fused time step of the whole grid (both lattices, streaming and
 boundary rules) on synthetic seeded input already resident in HBM.  Prints one
@@ -11,8 +12,10 @@ population storage (FP16 deviations by default), the HBM roofline of the step
 kernel, the same step with FP32 storage for comparison, the errors of the
 storage format against the FP64 oracle's reference values (coexistence
 densities, Laplace jump, D^2 slope), the batched step over 256 independent
-lattices of uneven size (aggregate MLUPS after autotuning), and the FP64
-oracle timed on the host as a CPU baseline.
+lattices of uneven size (aggregate MLUPS after autotuning), the same step with
+a D3Q19 temperature lattice against the D3Q7 one (the paper's efficiency
+argument for D3Q7, Sec. III B), and the FP64 oracle timed on the host as a
+CPU baseline.
 """
 import argparse
 import hashlib
@@ -32,12 +35,19 @@ HBM_PEAK_GBS = 8000.0
 # once and written once.
 BYTES_PER_LUP = {"f32": 2 * 26 * 4 + 8, "f64": 2 * 26 * 8 + 16, "f16": 2 * (26 * 2 + 2 * 2) + 8,
                  "bf16": 2 * (26 * 2 + 2 * 4) + 8, "f32dev": 2 * 28 * 4 + 8}
+# The same with a D3Q19 temperature lattice: 19 + 19 populations.
+BYTES_PER_LUP_Q19T = {"f32": 2 * 38 * 4 + 8, "f64": 2 * 38 * 8 + 16, "f16": 2 * (38 * 2 + 2 * 2) + 8}
+
+
+def bytes_per_lup(storage, q19t=False):
+    return (BYTES_PER_LUP_Q19T if q19t else BYTES_PER_LUP)[storage]
 PRECISION_BOUND = 1e-3
 KERNEL_SOURCES = ["paper_2201_06039_amd/csrc/lbm_kernels.hpp", "paper_2201_06039_amd/csrc/lbm_api.hip"]
 
 
-def traffic_file(workload, storage):
-    return os.path.join(ROOT, "profiles", f"k_step_{workload}_{storage}_traffic.json")
+def traffic_file(workload, storage, q19t=False):
+    tag = "_d3q19t" if q19t else ""
+    return os.path.join(ROOT, "profiles", f"k_step_{workload}_{storage}{tag}_traffic.json")
 
 
 def kernel_hash():
@@ -48,11 +58,11 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, storage, launch):
+def measured_traffic(workload, storage, launch, q19t=False):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source with the same workload and launch."""
     try:
-        with open(traffic_file(workload, storage)) as fh:
+        with open(traffic_file(workload, storage, q19t)) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -63,11 +73,11 @@ def measured_traffic(workload, storage, launch):
     return t.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(w, fields, seconds=15.0):
+def cpu_baseline(params, fields, seconds=15.0):
     """The FP64 oracle on the host cores, on the same workload, for a bounded
     number of steps sized to take about `seconds`."""
     from oracle import sim
-    s = sim.Sim(**w["params"])
+    s = sim.Sim(**params)
     s.init_fields(*fields)
     t0 = time.perf_counter()
     s.step(1)
@@ -81,7 +91,7 @@ def cpu_baseline(w, fields, seconds=15.0):
     s.close()
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(nn * n / (t1 - t0) / 1e6, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"{n} steps of the full {w['params']['nx']}x{w['params']['ny']}x{w['params']['nz']} grid "
+            "sample": f"{n} steps of the full {params['nx']}x{params['ny']}x{params['nz']} grid "
                       f"after 1 untimed step, FP64 C + OpenMP"}
 
 
@@ -168,6 +178,27 @@ def batch_run(storage, steps, warmup, name="batch_256", launch=None):
             "thread_slot_efficiency": round(nodes / slots, 4), "graph": True}
 
 
+def lattice_comparison(lbm, p, fields, steps, warmup, storages=("f16", "f32")):
+    """The step with the D3Q7 and the D3Q19 temperature lattice, both with the
+    BGK collision of Eq. (19) (the only one the paper specifies for both), on
+    the same workload and storage: measured speed ratio against the ratio of
+    algorithmic bytes per update."""
+    nn = p["nx"] * p["ny"] * p["nz"]
+    out = {}
+    for storage in storages:
+        row = {}
+        for name, extra in (("d3q7", dict(thermal_bgk=1)), ("d3q19", dict(thermal_bgk=1, thermal_lattice=1))):
+            ms, launch, _ = timed_run(lbm, dict(p, **extra), fields, storage, steps, warmup)
+            row[name] = {"MLUPS": round(nn * steps / (ms / 1e3) / 1e6, 2), "ms_per_step": round(ms / steps, 5),
+                         "bytes_per_lup": bytes_per_lup(storage, name == "d3q19"),
+                         "tile": [launch["tile_x"], launch["tile_y"]], "chunk_z": launch["chunk_z"]}
+            print(f"# temperature lattice {name} {storage}: {ms / steps:.5f} ms/step", file=sys.stderr, flush=True)
+        row["speedup_of_d3q7"] = round(row["d3q19"]["ms_per_step"] / row["d3q7"]["ms_per_step"], 3)
+        row["bytes_ratio"] = round(row["d3q19"]["bytes_per_lup"] / row["d3q7"]["bytes_per_lup"], 3)
+        out[storage] = row
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +208,8 @@ def main():
     ap.add_argument("--storage", default="f16", choices=sorted(BYTES_PER_LUP))
     ap.add_argument("--compare", default="f32", choices=sorted(BYTES_PER_LUP) + ["none"],
                     help="second storage format timed on the same workload")
+    ap.add_argument("--thermal-lattice", default="d3q7", choices=["d3q7", "d3q19"],
+                    help="temperature lattice of the timed step (d3q19 runs the BGK collision)")
     ap.add_argument("--tile", default=None, help="TXxTY, e.g. 64x4")
     ap.add_argument("--chunk", type=int, default=None)
     ap.add_argument("--no-precision", action="store_true")
@@ -186,6 +219,7 @@ def main():
     ap.add_argument("--batch-launch", default=None, metavar="TXxTYxCZxWG",
                     help="fixed batch launch (tile, chunk, workgroups) instead of the autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-lattice-comparison", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="only run 20 plain device-to-device copies of MB megabytes (to calibrate the "
                          "FETCH_SIZE/WRITE_SIZE counters against a kernel of known traffic) and exit")
@@ -225,7 +259,12 @@ def main():
 
     w = W.load(args.workload)
     fields = W.fields(w)
-    p = w["params"]
+    p = dict(w["params"])
+    q19t = args.thermal_lattice == "d3q19"
+    if q19t:
+        if args.storage not in BYTES_PER_LUP_Q19T:
+            ap.error(f"the D3Q19 temperature lattice is built for {sorted(BYTES_PER_LUP_Q19T)}")
+        p.update(thermal_lattice=1, thermal_bgk=1)
     nn = p["nx"] * p["ny"] * p["nz"]
 
     print(f"# workload {args.workload} {p['nx']}x{p['ny']}x{p['nz']} storage {args.storage}", file=sys.stderr,
@@ -236,7 +275,7 @@ def main():
     sec = ms / 1e3
     mlups = nn * args.steps / sec / 1e6
     avg_launch_s = sec / args.steps  # the step kernel is the only launch per step when launches == 1
-    bytes_alg = BYTES_PER_LUP[args.storage] * nn
+    bytes_alg = bytes_per_lup(args.storage, q19t) * nn
     achieved = bytes_alg / avg_launch_s / 1e9
     arith = "f64" if args.storage == "f64" else "f32"
     out = {
@@ -253,34 +292,38 @@ def main():
         "dtype": arith,
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": [p["nx"], p["ny"], p["nz"]], "storage": args.storage,
+                   "temperature_lattice": args.thermal_lattice.upper() + (" BGK" if q19t else " MRT"),
                    "tile": [launch["tile_x"], launch["tile_y"]], "chunk_z": launch["chunk_z"],
                    "workgroups": launch["workgroups"], "launches_per_step": launches},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(args.workload, args.storage, launch),
-                     "kernel": "k_step", "bytes_per_lup": BYTES_PER_LUP[args.storage]},
+                     "traffic": measured_traffic(args.workload, args.storage, launch, q19t),
+                     "kernel": "k_step", "bytes_per_lup": bytes_per_lup(args.storage, q19t)},
     }
-    if args.compare != "none" and args.compare != args.storage:
+    if args.compare != "none" and args.compare != args.storage and (not q19t or args.compare in BYTES_PER_LUP_Q19T):
         ms2, launch2, _ = timed_run(lbm, p, fields, args.compare, args.steps, args.warmup)
         print(f"# {args.compare}: {ms2 / args.steps:.5f} ms/step, launch {launch2}", file=sys.stderr, flush=True)
         sec2 = ms2 / 1e3 / args.steps
         out["compare"] = {"storage": args.compare, "value": round(nn / sec2 / 1e6, 2), "unit": "MLUPS",
                           "ms_per_step": round(ms2 / args.steps, 5),
-                          "roofline_frac": round(BYTES_PER_LUP[args.compare] * nn / sec2 / 1e9 / HBM_PEAK_GBS, 4),
-                          "bytes_per_lup": BYTES_PER_LUP[args.compare],
+                          "roofline_frac": round(bytes_per_lup(args.compare, q19t) * nn / sec2 / 1e9 / HBM_PEAK_GBS, 4),
+                          "bytes_per_lup": bytes_per_lup(args.compare, q19t),
                           "tile": [launch2["tile_x"], launch2["tile_y"]], "chunk_z": launch2["chunk_z"],
                           "speedup_of_storage": round(ms2 / ms, 3)}
-    if not args.no_precision:
+    if not args.no_lattice_comparison and not q19t:
+        out["temperature_lattice_comparison"] = lattice_comparison(lbm, p, fields, max(1, args.steps // 2),
+                                                                   args.warmup)
+    if not args.no_precision and not q19t:
         errs = precision_errors(args.storage)
         print(f"# precision of {args.storage}: {errs}", file=sys.stderr, flush=True)
         out["precision"] = {"storage": args.storage, "reference": "FP64 oracle", "bound": PRECISION_BOUND,
                             "relative_errors": errs, "within_bound": max(errs.values()) <= PRECISION_BOUND}
-    if not args.no_batch:
+    if not args.no_batch and not q19t:
         bl = tuple(int(v) for v in args.batch_launch.split("x")) if args.batch_launch else None
         out["batch"] = batch_run(args.storage if args.storage != "f64" else "f32", args.batch_steps, 10, launch=bl)
         print(f"# batch: {out['batch']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, fields)
+        out["cpu_baseline"] = cpu_baseline(p, fields)
     print(json.dumps(out), flush=True)
 
 

@@ -8,7 +8,9 @@
  *     (Sec. II, Eqs. (1)-(10)) with the Peng-Robinson EOS (Sec. IV A, Eq. (49));
  *   - D3Q7 MRT lattice for temperature (Sec. III C, Eqs. (37)-(43)) whose
  *     source phi_s (Sec. III A, Eq. (18)) uses the local temperature gradient
- *     of Eq. (45) and the local velocity divergence of Eq. (48);
+ *     of Eq. (45) and the local velocity divergence of Eq. (48); as options
+ *     the BGK collision of Eq. (19) with the gradient of Eq. (36), on D3Q7 or
+ *     on a D3Q19 temperature lattice (Sec. III B);
  *   - halfway bounce-back (Eq. (50)) and anti-bounce-back (Eq. (51)) at a
  *     bottom wall, an open top, and buoyancy F_b = (rho - rho_ave) g (Sec. IV C).
  *
@@ -55,12 +57,19 @@ extern "C" {
 #define LBM_KAPPA_CONST_LAMBDA 0 /* kappa is lambda; chi varies with rho per node */
 #define LBM_KAPPA_CONST_CHI 1    /* kappa is chi itself                           */
 
+/* Temperature lattice (Sec. III B). */
+#define LBM_THERMAL_D3Q7 0  /* Eq. (21); weights 1 - d, d/6; c_sT^2 = d/3          */
+#define LBM_THERMAL_D3Q19 1 /* the D3Q19 velocities of Eq. (2) with the standard   */
+                            /* weights 1/3, 1/18, 1/36 and c_sT^2 = 1/3; BGK only */
+                            /* (thermal_bgk = 1); storage F32, F64 or F16; not in */
+                            /* batches                                            */
+
 /* Storage format of the populations.
  *   F32, F64: the populations f, g themselves; arithmetic in the same type.
  *   F16, BF16, F32_DEV: deviations from the rest equilibrium of a per-node
  *     reference, e = (f_alpha - w_alpha rho_r) s and r = (g_alpha - w_alpha T_r) s,
  *     with w_alpha the weights of Eq. (5) at u = 0 (1/3, 1/18, 1/36) and of
- *     the D3Q7 lattice (1 - d, d/6), in the storage type.  rho_r and T_r are
+ *     the temperature lattice (1 - d, d/6 on D3Q7), in the storage type.  rho_r and T_r are
  *     the node's density and temperature one step earlier, stored as two more
  *     planes (FP16 for F16, FP32 for BF16 and F32_DEV); s = 1024 for F16
  *     (keeps small deviations out of the subnormal range), 1 otherwise.
@@ -110,12 +119,14 @@ typedef struct lbm_params {
                              /* tau_g = 1/2 + chi/c_sT^2 for every moment (the */
                              /* MRT one with varsigma_q = varsigma_pi = tau_g),*/
                              /* grad T from Eq. (36)                           */
+    int thermal_lattice;     /* LBM_THERMAL_*; D3Q19 stores 19 g planes        */
+                             /* instead of 7 (38 population planes, not 26)   */
 } lbm_params;
 
 typedef struct lbm_handle lbm_handle;
 
 /* Device bytes the arena must hold for these parameters (0 if invalid).
- * Layout: two copies (ping-pong) of the 19 + 7 population planes (and, for
+ * Layout: two copies (ping-pong) of the 19 + QT population planes (and, for
  * the deviation formats, the rho_r and T_r planes), the phi_s history plane
  * (FP32, FP64 for F64 storage), six FP64 staging planes for init and readout,
  * block partial sums and a few scalars, each region 256-byte aligned.
@@ -191,7 +202,8 @@ const char *lbm_strerror(int status);
  *
  * Restrictions (EINVAL otherwise): 1 <= ncases <= 65536, every lattice valid
  * for lbm_create, the same `storage` for all, bc_z = LBM_BC_PERIODIC, no
- * gravity (g = 0; the reservoir boundary bc_T_shell is allowed).
+ * gravity (g = 0; the reservoir boundary bc_T_shell is allowed), the D3Q7
+ * temperature lattice.
  * --------------------------------------------------------------------------- */
 typedef struct lbm_batch lbm_batch;
 

@@ -27,6 +27,8 @@ constexpr TileShape kTiles[] = {{64, 4}, {32, 8}, {64, 8}, {32, 16}, {128, 4}};
 
 struct Layout {
     size_t nn, stride, es, rs, cs, planes;
+    size_t npop;   // population planes: 19 + velocities of the temperature lattice
+    int qt;        // 7 (D3Q7) or 19 (D3Q19)
     size_t off_pop[2], off_phi, off_stage, off_part, off_scal, total;
     size_t max_partials;
 };
@@ -43,9 +45,12 @@ size_t element_bytes(int s) {
     return 4;
 }
 
-// Planes per copy: 26 populations, plus rho_r and T_r for the deviation
+// Velocities of the temperature lattice.
+int thermal_q(const lbm_params *p) { return p->thermal_lattice == LBM_THERMAL_D3Q19 ? 19 : 7; }
+
+// Planes per copy: 19 + QT populations, plus rho_r and T_r for the deviation
 // formats (FP16 for F16, FP32 for BF16 and F32_DEV).
-size_t planes_of(int s) { return (s == LBM_STORE_F32 || s == LBM_STORE_F64) ? 26 : 28; }
+size_t planes_of(int s, int qt) { return 19 + qt + ((s == LBM_STORE_F32 || s == LBM_STORE_F64) ? 0 : 2); }
 size_t reference_bytes(int s) { return s == LBM_STORE_F64 ? 8 : (s == LBM_STORE_F16 ? 2 : 4); }
 
 bool valid_params(const lbm_params *p) {
@@ -66,6 +71,12 @@ bool valid_params(const lbm_params *p) {
     if (p->thermal != 0 && p->thermal != 1) return false;
     if (p->bc_T_shell != 0 && p->bc_T_shell != 1) return false;
     if (p->thermal_bgk != 0 && p->thermal_bgk != 1) return false;
+    // The paper gives relaxation rates for the D3Q7 moments only: the D3Q19
+    // temperature lattice takes the BGK collision.
+    if (p->thermal_lattice != LBM_THERMAL_D3Q7 && p->thermal_lattice != LBM_THERMAL_D3Q19) return false;
+    if (p->thermal_lattice == LBM_THERMAL_D3Q19 &&
+        (!p->thermal_bgk || p->storage == LBM_STORE_BF16 || p->storage == LBM_STORE_F32_DEV))
+        return false;
     if (p->bc_T_shell && (p->bc_z != LBM_BC_PERIODIC || !p->thermal || !(p->T_shell > 0.0))) return false;
     return true;
 }
@@ -81,28 +92,29 @@ size_t max_workgroups(const lbm_params *p) {
     return best > sum_blocks ? best : sum_blocks;
 }
 
-size_t copy_bytes(const Layout &L) { return L.stride * (26 * L.es + (L.planes - 26) * L.rs); }
+size_t copy_bytes(const Layout &L) { return L.stride * (L.npop * L.es + (L.planes - L.npop) * L.rs); }
 
-// Physical planes of a copy, as stored: the plain layout (FP64) has the 26
-// population planes; the paired layout (2- and 4-byte elements) has 13
+// Physical planes of a copy, as stored: the plain layout (FP64) has the npop
+// population planes; the paired layout (2- and 4-byte elements) has npop / 2
 // planes of population pairs, then (deviation formats) one pair plane of
 // references as wide as the populations, or two planes of wider ones.
 bool paired(const Layout &L) { return L.es == 2 || L.es == 4; }
-bool refs_in_pair(const Layout &L) { return L.planes == 28 && L.rs == L.es; }
+bool refs_in_pair(const Layout &L) { return L.planes == L.npop + 2 && L.rs == L.es; }
 size_t phys_planes(const Layout &L) {
     if (!paired(L)) return L.planes;
-    return 13 + (L.planes == 28 ? (refs_in_pair(L) ? 1 : 2) : 0);
+    return L.npop / 2 + (L.planes == L.npop + 2 ? (refs_in_pair(L) ? 1 : 2) : 0);
 }
 size_t plane_offset(const Layout &L, size_t k) {
+    const size_t np = L.npop;
     if (paired(L)) {
-        if (k < 13 || refs_in_pair(L)) return k * L.stride * 2 * L.es;
-        return 26 * L.stride * L.es + (k - 13) * L.stride * L.rs;
+        if (k < np / 2 || refs_in_pair(L)) return k * L.stride * 2 * L.es;
+        return np * L.stride * L.es + (k - np / 2) * L.stride * L.rs;
     }
-    return k < 26 ? k * L.stride * L.es : 26 * L.stride * L.es + (k - 26) * L.stride * L.rs;
+    return k < np ? k * L.stride * L.es : np * L.stride * L.es + (k - np) * L.stride * L.rs;
 }
 size_t plane_bytes(const Layout &L, size_t k) {
-    if (paired(L)) return (k < 13 || refs_in_pair(L)) ? L.nn * 2 * L.es : L.nn * L.rs;
-    return L.nn * (k < 26 ? L.es : L.rs);
+    if (paired(L)) return (k < L.npop / 2 || refs_in_pair(L)) ? L.nn * 2 * L.es : L.nn * L.rs;
+    return L.nn * (k < L.npop ? L.es : L.rs);
 }
 
 Layout make_layout(const lbm_params *p) {
@@ -111,10 +123,12 @@ Layout make_layout(const lbm_params *p) {
     L.es = element_bytes(p->storage);
     L.cs = p->storage == LBM_STORE_F64 ? 8 : 4;
     L.rs = reference_bytes(p->storage);
-    L.planes = planes_of(p->storage);
+    L.qt = thermal_q(p);
+    L.npop = 19 + L.qt;
+    L.planes = planes_of(p->storage, L.qt);
     L.stride = align_up(L.nn, 128);
     // Each ping-pong copy holds its planes contiguously, `stride` elements
-    // apart: f_0..f_18, g_0..g_6, then (deviation formats) rho_r and T_r.
+    // apart: f_0..f_18, g_0..g_{QT-1}, then (deviation formats) rho_r and T_r.
     size_t off = 0;
     for (int k = 0; k < 2; ++k) {
         L.off_pop[k] = off;
@@ -154,10 +168,19 @@ lbm::Phys<C> make_phys(const lbm_params *p) {
     P.divu_b = (C)(1.0 - 1.0 / (2.0 * p->tau_e));
     P.cV = (C)p->cV;
     P.inv_cV = (C)(1.0 / p->cV);
-    P.wT0 = (C)(1.0 - p->d);
-    P.wT1 = (C)(p->d / 6.0);
-    P.csT2 = (C)(p->d / 3.0);
-    P.inv_csT2 = (C)(3.0 / p->d);
+    if (thermal_q(p) == 7) {
+        // Sec. III B, Eq. (22): w0 = 1 - d, w1..6 = d/6, c_sT^2 = d/3.
+        P.wT0 = (C)(1.0 - p->d);
+        P.wT1 = (C)(p->d / 6.0);
+        P.csT2 = (C)(p->d / 3.0);
+        P.inv_csT2 = (C)(3.0 / p->d);
+    } else {
+        // D3Q19: the standard weights and c_sT^2 = c_s^2 = 1/3.
+        P.wT0 = (C)(1.0 / 3.0);
+        P.wT1 = (C)(1.0 / 18.0);
+        P.csT2 = (C)(1.0 / 3.0);
+        P.inv_csT2 = (C)3.0;
+    }
     P.d = (C)p->d;
     P.kappa = (C)p->kappa;
     P.gam_q = (C)(1.0 / p->vs_q);
@@ -188,17 +211,27 @@ struct StateHeader {
 };
 constexpr int32_t kStateVersion = 3;
 
-// Calls fn with a value of the storage-format type of `storage`.
-template <typename Fn>
-int with_format(int storage, Fn &&fn) {
+// Calls fn with a value of the format type of `storage` for a temperature
+// lattice of QT velocities.
+template <int QT, typename Fn>
+int with_format_q(int storage, Fn &&fn) {
     switch (storage) {
-    case LBM_STORE_F32: return fn(lbm::StoreF32{});
-    case LBM_STORE_F64: return fn(lbm::StoreF64{});
-    case LBM_STORE_F16: return fn(lbm::StoreF16{});
-    case LBM_STORE_BF16: return fn(lbm::StoreBF16{});
-    case LBM_STORE_F32_DEV: return fn(lbm::StoreF32Dev{});
+    case LBM_STORE_F32: return fn(lbm::Fmt<lbm::StoreF32, QT>{});
+    case LBM_STORE_F64: return fn(lbm::Fmt<lbm::StoreF64, QT>{});
+    case LBM_STORE_F16: return fn(lbm::Fmt<lbm::StoreF16, QT>{});
+    }
+    if constexpr (QT == 7) {  // the comparison formats are built for D3Q7 only
+        if (storage == LBM_STORE_BF16) return fn(lbm::Fmt<lbm::StoreBF16, QT>{});
+        if (storage == LBM_STORE_F32_DEV) return fn(lbm::Fmt<lbm::StoreF32Dev, QT>{});
     }
     return LBM_EINVAL;
+}
+
+// The same for a lattice's own storage format and temperature lattice.
+template <typename Fn>
+int with_format(const lbm_params &p, Fn &&fn) {
+    if (thermal_q(&p) == 19) return with_format_q<19>(p.storage, fn);
+    return with_format_q<7>(p.storage, fn);
 }
 
 }  // namespace
@@ -252,6 +285,13 @@ void set_default_launch(lbm_handle *h) {
         h->tile_x = 32;
         h->tile_y = 8;
     }
+    if (h->L.qt == 19 && nx > 32) {
+        // D3Q19 temperature lattice (measured at 128^3): FP32 holds its 38
+        // populations per node without spilling only in 256-thread tiles;
+        // FP16 runs best with whole 128-node rows.
+        h->tile_x = (half && nx >= 96) ? 128 : 64;
+        h->tile_y = 4;
+    }
     if (h->p.storage == LBM_STORE_F64 && h->tile_x * h->tile_y != 256) {
         h->tile_x = nx > 32 ? 64 : 32;
         h->tile_y = nx > 32 ? 4 : 8;
@@ -272,7 +312,8 @@ int workgroups_for(const lbm_handle *h, int tx, int ty, int cz) {
 // The buffer-resource path addresses each half of a copy's planes (split at
 // plane 14) with 32-bit offsets.
 bool buffer_path(const Layout &L) {
-    const size_t lo = (size_t)lbm::kSplitPlane * L.stride * L.es;
+    const size_t split = L.qt == 19 ? lbm::PopLayout<19>::kSplit : lbm::PopLayout<7>::kSplit;
+    const size_t lo = split * L.stride * L.es;
     const size_t hi = copy_bytes(L) - lo;
     return lo <= 0xFFFFFFFFull && hi <= 0xFFFFFFFFull;
 }
@@ -426,7 +467,7 @@ int init_state(lbm_handle *h, const double *rho, const double *ux, const double 
     const lbm::Phys<double> P = make_phys<double>(&h->p);
     const int nb = (int)((nn + 255) / 256);
     h->cur = copy;
-    rc = with_format(h->p.storage, [&](auto fmt) {
+    rc = with_format(h->p, [&](auto fmt) {
         using ST = decltype(fmt);
         hipLaunchKernelGGL(lbm::k_init<ST>, dim3(nb), dim3(256), 0, h->stream, (const double *)st, nn,
                            (typename ST::T *)h->pop(copy), (typename ST::C *)h->phi(), h->L.stride, P, h->status());
@@ -459,7 +500,7 @@ int lbm_step(lbm_handle *h, int n) {
     if (!h || n < 0) return LBM_EINVAL;
     if (!h->initialized) return LBM_ESTATE;
     for (int k = 0; k < n; ++k) {
-        const int rc = with_format(h->p.storage, [&](auto fmt) { return step_once<decltype(fmt)>(h); });
+        const int rc = with_format(h->p, [&](auto fmt) { return step_once<decltype(fmt)>(h); });
         if (rc) return rc;
     }
     return LBM_OK;
@@ -473,7 +514,7 @@ int lbm_get_rho_u_T(lbm_handle *h, double *rho, double *ux, double *uy, double *
     const lbm::Phys<double> P = make_phys<double>(&h->p);
     double *st = h->stage();
     const int walls = h->p.bc_z == LBM_BC_WALL_BOTTOM_OPEN_TOP;
-    const int lrc = with_format(h->p.storage, [&](auto fmt) {
+    const int lrc = with_format(h->p, [&](auto fmt) {
         using ST = decltype(fmt);
         const typename ST::T *pop = (const typename ST::T *)h->pop(h->cur);
         hipLaunchKernelGGL(lbm::k_macro<ST>, dim3(nb), dim3(256), 0, h->stream, pop, h->L.stride, nn, P, st);
@@ -500,7 +541,7 @@ int lbm_get_rho_u_T(lbm_handle *h, double *rho, double *ux, double *uy, double *
 int lbm_reduce(lbm_handle *h, double *mass, double *energy) {
     if (!h || !mass || !energy) return LBM_EINVAL;
     if (!h->initialized) return LBM_ESTATE;
-    int rc = with_format(h->p.storage, [&](auto fmt) { return reduce_state<decltype(fmt)>(h, false); });
+    int rc = with_format(h->p, [&](auto fmt) { return reduce_state<decltype(fmt)>(h, false); });
     if (rc) return rc;
     double me[2];
     if (hipMemcpyAsync(me, h->mass(), 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess)
@@ -676,6 +717,7 @@ bool valid_batch(const lbm_params *cases, int n) {
         const lbm_params *p = cases + c;
         if (!valid_params(p) || p->storage != cases[0].storage || p->bc_z != LBM_BC_PERIODIC) return false;
         if (p->g[0] != 0.0 || p->g[1] != 0.0 || p->g[2] != 0.0) return false;
+        if (p->thermal_lattice != LBM_THERMAL_D3Q7) return false;  // the batched kernel is built for D3Q7
     }
     return true;
 }
@@ -844,12 +886,12 @@ int launch_batch(lbm_batch *b, int parity) {
 }
 
 int batch_launch_one(lbm_batch *b, int parity) {
-    return with_format(b->storage, [&](auto fmt) { return launch_batch<decltype(fmt)>(b, parity); });
+    return with_format_q<7>(b->storage, [&](auto fmt) { return launch_batch<decltype(fmt)>(b, parity); });
 }
 
 int batch_tables(lbm_batch *b) {
     drop_graphs(b);
-    return with_format(b->storage, [&](auto fmt) { return build_batch_tables<decltype(fmt)>(b); });
+    return with_format_q<7>(b->storage, [&](auto fmt) { return build_batch_tables<decltype(fmt)>(b); });
 }
 
 // Graph of two steps starting from population copy `from`.

@@ -1,7 +1,9 @@
 // Device code of liblbm for gfx950 (MI355X): the fused D3Q19 + D3Q7 time step
-// of Li, Yu & Luo (arXiv:2201.06039) and its helper kernels.
+// of Li, Yu & Luo (arXiv:2201.06039) and its helper kernels.  The temperature
+// lattice may also be D3Q19 (standard weights, BGK collision of Eq. (19)).
 //
-// State layout in HBM (structure of arrays, x fastest), two ping-pong copies:
+// State layout in HBM (structure of arrays, x fastest), two ping-pong copies
+// (D3Q7 temperature lattice; D3Q19: g on planes 19..37, references 38, 39):
 //   plane  0..18   D3Q19 populations f_alpha at time t (post-streaming)
 //   plane 19..25   D3Q7 populations g_alpha
 //   plane 26, 27   (deviation storage only) per-node references rho_r, T_r
@@ -113,6 +115,13 @@ __device__ __forceinline__ C sum19(const C *f) {
 template <typename C>
 __device__ __forceinline__ C sum7(const C *g) {
     return g[0] + ((g[1] + g[2]) + (g[3] + g[4]) + (g[5] + g[6]));
+}
+
+// T = sum g over the QT velocities of the temperature lattice.
+template <int QT, typename C>
+__device__ __forceinline__ C sum_T(const C *g) {
+    if constexpr (QT == 7) return sum7(g);
+    else return sum19(g);
 }
 
 // m = M f for the raw monomial basis (1, e, |e|^2, 2ex^2-ey^2-ez^2, ey^2-ez^2,
@@ -317,6 +326,14 @@ struct StoreBF16 {  // conversions round to nearest even (v_cvt_pk_bf16_f32 on g
     __device__ static T denc(double v) { return (T)(float)v; }
 };
 
+// A storage format for a temperature lattice of QT = 7 (D3Q7, Sec. III B) or
+// QT = 19 (D3Q19 with the standard weights) velocities.
+template <typename Base, int QT>
+struct Fmt : Base {
+    static_assert(QT == 7 || QT == 19, "temperature lattice");
+    static constexpr int kQT = QT;
+};
+
 // Loads/stores of a 2-, 4- or 8-byte element through a buffer resource.
 template <typename T>
 __device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
@@ -338,34 +355,29 @@ __device__ __forceinline__ void buf_st(T x, __amdgpu_buffer_rsrc_t r, unsigned v
 
 constexpr int kBufferFlags = 0x00020000;  // raw dword buffer; the record count is left at its maximum and
                                           // every offset is kept inside the planes by construction
-constexpr int kSplitPlane = 14;           // population planes [0,14) and [14,26) + references: two resources
-constexpr int kPopPlanes = 26;
 
 // Access to the planes of the two ping-pong copies.
 //
-// Plain layout (4- and 8-byte elements): 26 population planes of T, `stride`
-// elements apart, then (deviation formats) the rho_r and T_r planes of R.
+// Plain layout (8-byte elements): the kPop = 19 + QT population planes of T,
+// `stride` elements apart, then (deviation formats) the rho_r and T_r planes
+// of R.
 //
-// Paired layout (2-byte elements): two populations share one plane of 32-bit
-// words, so a node's values arrive in 14 four-byte loads instead of 28
-// two-byte ones (the step kernel is limited by how many loads it keeps in
-// flight, and two-byte loads halve the bytes each one moves).  The pairs are
-// chosen for the push stores: f_a and g_a of the same velocity (a = 0..6)
-// go to the same neighbour and are written as one word; the diagonal f pair
-// up with a partner of the same e_z, whose half is written in the same
-// z-plane pass, so both halves of a word reach L2 close together; 16-bit
-// references (rho_r, T_r) form the last pair.  32-bit references (BF16)
-// follow the 13 pair planes.  Population index a: 0..18 f, 19..25 g, 26..27
-// the references.
+// Paired layout (2- and 4-byte elements): two populations share one plane of
+// words twice their width, so a node's values arrive in kPop / 2 wide loads
+// (the step kernel is limited by how many loads it keeps in flight).  The
+// pairs are chosen for the push stores (PopLayout): f_a and g_a of the same
+// velocity go to the same neighbour and are written as one word.  16-bit
+// references (rho_r, T_r) form the last pair; 32-bit references (BF16)
+// follow the kPop / 2 pair planes.
 //
 // Every access names a population (or reference) index, a per-thread byte
 // offset `v` (the node's place inside an x-y plane) and a workgroup-uniform
 // byte offset `s` (the z plane), both counted in node strides of the layout
-// (4 bytes per node in a pair plane).
+// (two elements per node in a pair plane).
 //  BUF = true: two buffer resources per copy (planes below byte offset
-//  14 * stride * sizeof(T), and the rest); plane and z offsets go into the
-//  scalar offset, the x-y offset is the one vector offset and the half of a
-//  word a constant, so loads and stores cost no vector address arithmetic.
+//  kSplit * stride * sizeof(T), and the rest); plane and z offsets go into
+//  the scalar offset, the x-y offset is the one vector offset and the half of
+//  a word a constant, so loads and stores cost no vector address arithmetic.
 //  Needs each half to span less than 4 GiB.
 //  BUF = false: plain global pointers (any size).
 template <typename T>
@@ -385,28 +397,60 @@ __device__ __forceinline__ T pair_half(PairWord<T> w, int h) {
     return __builtin_bit_cast(T, (H)(h ? w >> (8 * sizeof(T)) : w));
 }
 
-// Members (low half, high half) of pair plane p, and the pair and half of
-// population a.
-constexpr int kPairMember[14][2] = {{0, 19}, {1, 20}, {2, 21}, {3, 22}, {4, 23}, {5, 24}, {6, 25},
-                                    {7, 8},  {9, 10}, {11, 14}, {15, 18}, {12, 13}, {16, 17}, {26, 27}};
-constexpr int kPairOf[28] = {0, 1, 2, 3, 4, 5, 6, 7, 7, 8, 8, 9, 11, 11, 9, 10, 12, 12, 10,
-                             0, 1, 2, 3, 4, 5, 6, 13, 13};
-constexpr int kHalfOf[28] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 0, 1, 0, 0, 1, 1, 0, 0, 1, 1,
-                             1, 1, 1, 1, 1, 1, 1, 0, 1};
-constexpr bool pair_tables_consistent() {
-    for (int p = 0; p < 14; ++p)
-        for (int h = 0; h < 2; ++h)
-            if (kPairOf[kPairMember[p][h]] != p || kHalfOf[kPairMember[p][h]] != h) return false;
-    return true;
-}
-static_assert(pair_tables_consistent(), "pair tables disagree");
-constexpr int kPairSplit = kSplitPlane / 2;  // pairs [0,7) behind the low resource
+// Population planes of a copy for a temperature lattice of QT = 7 (D3Q7) or
+// 19 (D3Q19) velocities: f_0..f_18 are planes 0..18, g_0..g_{QT-1} follow
+// from plane 19, and the references rho_r, T_r are the planes kPop, kPop + 1.
+// In the paired layout pair plane p holds populations member(p, 0) (low
+// half) and member(p, 1); population a sits in pair pair_of(a), half
+// half_of(a).  The last pair holds references as wide as the populations.
+//  D3Q7: f_a with g_a for a = 0..6; the diagonal f pair with a partner of
+//   the same e_z, whose half is written in the same z-plane pass.
+//  D3Q19: f_a with g_a for every a, so each push store writes a whole word.
+// Two buffer resources cover a copy: planes [0, kSplit) (pairs
+// [0, kSplit / 2)) behind the first, the rest and the references behind the
+// second.
+template <int QT>
+struct PopLayout;
 
-template <typename T, typename R, bool BUF>
+template <>
+struct PopLayout<7> {
+    static constexpr int kQT = 7, kPop = 26, kPairs = 14, kSplit = 14;
+    static constexpr int kMember[14][2] = {{0, 19}, {1, 20}, {2, 21}, {3, 22}, {4, 23}, {5, 24}, {6, 25},
+                                           {7, 8},  {9, 10}, {11, 14}, {15, 18}, {12, 13}, {16, 17}, {26, 27}};
+    static constexpr int kPairOf[28] = {0, 1, 2, 3, 4, 5, 6, 7, 7, 8, 8, 9, 11, 11, 9, 10, 12, 12, 10,
+                                        0, 1, 2, 3, 4, 5, 6, 13, 13};
+    static constexpr int kHalfOf[28] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 0, 1, 0, 0, 1, 1, 0, 0, 1, 1,
+                                        1, 1, 1, 1, 1, 1, 1, 0, 1};
+    __host__ __device__ static constexpr int member(int p, int h) { return kMember[p][h]; }
+    __host__ __device__ static constexpr int pair_of(int a) { return kPairOf[a]; }
+    __host__ __device__ static constexpr int half_of(int a) { return kHalfOf[a]; }
+};
+
+template <>
+struct PopLayout<19> {
+    static constexpr int kQT = 19, kPop = 38, kPairs = 20, kSplit = 20;
+    __host__ __device__ static constexpr int member(int p, int h) { return p < 19 ? p + 19 * h : 38 + h; }
+    __host__ __device__ static constexpr int pair_of(int a) { return a < 19 ? a : (a < 38 ? a - 19 : 19); }
+    __host__ __device__ static constexpr int half_of(int a) { return a < 19 ? 0 : (a < 38 ? 1 : a - 38); }
+};
+
+template <int QT>
+constexpr bool pair_tables_consistent() {
+    using L = PopLayout<QT>;
+    for (int p = 0; p < L::kPairs; ++p)
+        for (int h = 0; h < 2; ++h)
+            if (L::pair_of(L::member(p, h)) != p || L::half_of(L::member(p, h)) != h) return false;
+    return L::kPairs == L::kPop / 2 + 1 && L::kSplit % 2 == 0;
+}
+static_assert(pair_tables_consistent<7>() && pair_tables_consistent<19>(), "pair tables disagree");
+
+template <typename T, typename R, bool BUF, int QT>
 struct PopIO;
 
-template <typename T, typename R>
-struct PopIO<T, R, true> {
+template <typename T, typename R, int QT>
+struct PopIO<T, R, true, QT> {
+    using L = PopLayout<QT>;
+    static constexpr int kSplitPlane = L::kSplit, kPairSplit = L::kSplit / 2, kPopPlanes = L::kPop;
     static constexpr bool PAIR = paired_layout<T>();
     __amdgpu_buffer_rsrc_t in_lo, in_hi, out_lo, out_hi;
     unsigned sb;   // population plane stride in bytes (plain layout) or pair plane stride / 2
@@ -420,25 +464,25 @@ struct PopIO<T, R, true> {
         out_hi = __builtin_amdgcn_make_buffer_rsrc(pout + kSplitPlane * stride, 0, -1, kBufferFlags);
     }
     // Whether population a sits behind the low resource, and the byte offset
-    // of its plane from that resource's base (pair plane kPairOf[a], 2 sb
+    // of its plane from that resource's base (pair plane pair_of(a), 2 sb
     // bytes wide, in the paired layout).
-    __device__ static constexpr bool low(int a) { return PAIR ? kPairOf[a] < kPairSplit : a < kSplitPlane; }
+    __device__ static constexpr bool low(int a) { return PAIR ? L::pair_of(a) < kPairSplit : a < kSplitPlane; }
     __device__ unsigned plane_off(int a) const {
         if constexpr (PAIR) {
-            const int p = kPairOf[a];
+            const int p = L::pair_of(a);
             return (unsigned)(p < kPairSplit ? p : p - kPairSplit) * 2u * sb;
         } else {
             return (unsigned)(a < kSplitPlane ? a : a - kSplitPlane) * sb;
         }
     }
-    __device__ static constexpr unsigned half_off(int a) { return PAIR ? (unsigned)(kHalfOf[a] * sizeof(T)) : 0u; }
+    __device__ static constexpr unsigned half_off(int a) { return PAIR ? (unsigned)(L::half_of(a) * sizeof(T)) : 0u; }
     __device__ T load(int a, unsigned v, unsigned s) const {
         return low(a) ? buf_ld<T>(in_lo, v + half_off(a), plane_off(a) + s)
                       : buf_ld<T>(in_hi, v + half_off(a), plane_off(a) + s);
     }
     // Both halves of pair plane p (paired layout only).
     __device__ PairWord<T> load_pair(int p, unsigned v, unsigned s) const {
-        const int a = kPairMember[p][0];
+        const int a = L::member(p, 0);
         return low(a) ? buf_ld<PairWord<T>>(in_lo, v, plane_off(a) + s) : buf_ld<PairWord<T>>(in_hi, v, plane_off(a) + s);
     }
     __device__ void store(int a, unsigned v, unsigned s, T x) const {
@@ -446,7 +490,7 @@ struct PopIO<T, R, true> {
         else buf_st<T>(x, out_hi, v + half_off(a), plane_off(a) + s);
     }
     __device__ void store_pair(int p, unsigned v, unsigned s, PairWord<T> w) const {
-        const int a = kPairMember[p][0];
+        const int a = L::member(p, 0);
         if (low(a)) buf_st<PairWord<T>>(w, out_lo, v, plane_off(a) + s);
         else buf_st<PairWord<T>>(w, out_hi, v, plane_off(a) + s);
     }
@@ -463,15 +507,17 @@ struct PopIO<T, R, true> {
     }
 };
 
-template <typename T, typename R>
-struct PopIO<T, R, false> {
+template <typename T, typename R, int QT>
+struct PopIO<T, R, false, QT> {
+    using L = PopLayout<QT>;
+    static constexpr int kPopPlanes = L::kPop;
     static constexpr bool PAIR = paired_layout<T>();
     const T *in;
     T *out;
     size_t st;
     __device__ PopIO(const T *pin, T *pout, size_t stride) : in(pin), out(pout), st(stride) {}
     __device__ size_t plane_elems(int a) const {
-        return PAIR ? (size_t)kPairOf[a] * 2 * st + kHalfOf[a] : a * st;
+        return PAIR ? (size_t)L::pair_of(a) * 2 * st + L::half_of(a) : a * st;
     }
     __device__ T load(int a, unsigned v, unsigned s) const {
         return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(in + plane_elems(a)) + s + v);
@@ -500,11 +546,12 @@ struct PopIO<T, R, false> {
     }
 };
 
-// Element index of population a (or reference plane 26 + k) of node i in a
-// copy, for the one-thread-per-node helper kernels.
-template <typename T>
+// Element index of population a (or reference plane kPop + k) of node i in
+// a copy, for the one-thread-per-node helper kernels.
+template <typename T, int QT>
 __host__ __device__ inline size_t element_index(int a, size_t st, size_t i) {
-    if constexpr (paired_layout<T>()) return (size_t)kPairOf[a] * 2 * st + 2 * i + kHalfOf[a];
+    using L = PopLayout<QT>;
+    if constexpr (paired_layout<T>()) return (size_t)L::pair_of(a) * 2 * st + 2 * i + L::half_of(a);
     else return (size_t)a * st + i;
 }
 
@@ -533,14 +580,14 @@ __device__ __forceinline__ int xcd_logical_block(int b, int nb) {
 // One node's loaded state in the compute type: e, r = stored f and g values
 // (K-scaled deviations for the deviation formats), br/bt = references
 // (0 for plain storage).
-template <typename C>
+template <typename C, int QT>
 struct NodePops {
-    C e[19], r[7], br, bt;
+    C e[19], r[QT], br, bt;
 };
 
-// A node's state as it arrives from memory in the paired layout: the 32-bit
-// words (13 of population pairs, a 14th of 16-bit references) and, for
-// 32-bit references, the references in the compute type.  Planes in flight
+// A node's state as it arrives from memory in the paired layout: the pair
+// words (kPop / 2 of population pairs, one more of 16-bit references) and,
+// for 32-bit references, the references in the compute type.  Planes in flight
 // are kept in this form and decoded where they are used, which halves the
 // registers they occupy.
 template <typename C, typename W, int WORDS>
@@ -560,9 +607,11 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     constexpr C K = ST::kScale, IK = C(1) / ST::kScale;
     constexpr int NT = TX * TY, EX = TX + 2, EY = TY + 2, NE = EX * EY, NH = NE - NT;
     static_assert(NH <= NT, "halo must not exceed the tile");
+    constexpr int QT = ST::kQT;  // velocities of the temperature lattice
+    using LY = PopLayout<QT>;
     constexpr bool PAIR = paired_layout<E>();
     constexpr unsigned NS = PAIR ? 2 * sizeof(E) : sizeof(E);  // bytes between neighbouring nodes of a plane
-    constexpr int G0 = 19;  // first D3Q7 plane
+    constexpr int G0 = 19;  // first temperature plane
     constexpr unsigned RSZ = sizeof(typename ST::R);
     // node stride of the reference planes: 16-bit references share a pair plane
     constexpr bool REF_IN_PAIR = ST::kDev && sizeof(typename ST::R) == sizeof(E) && paired_layout<E>();
@@ -592,7 +641,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     }
     const int nx = A.nx, ny = A.ny, nz = A.nz;
     const unsigned plane = (unsigned)nx * (unsigned)ny;
-    const PopIO<E, typename ST::R, BUF> io(A.pop_in, A.pop_out, A.stride);
+    const PopIO<E, typename ST::R, BUF, QT> io(A.pop_in, A.pop_out, A.stride);
 
     const int itx = logical % A.ntx;
     const int rest = logical / A.ntx;
@@ -632,27 +681,28 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         return zz < 0 ? zz + nz : zz;
     };
 
-    // 13 words hold f_0..f_18, g_0..g_6; references of the element's width
-    // are the 14th.
-    constexpr int WORDS = REF_IN_PAIR ? 14 : 13;
-    using Node = std::conditional_t<PAIR, NodeWords<C, PairWord<E>, WORDS>, NodePops<C>>;
+    // kPop / 2 words hold f_0..f_18, g_0..g_{QT-1}; references of the
+    // element's width are one more.
+    constexpr int WORDS = REF_IN_PAIR ? LY::kPairs : LY::kPairs - 1;
+    using Pops = NodePops<C, QT>;
+    using Node = std::conditional_t<PAIR, NodeWords<C, PairWord<E>, WORDS>, Pops>;
     // The node's values in the compute type.
-    auto decode = [&](const Node &n) -> NodePops<C> {
+    auto decode = [&](const Node &n) -> Pops {
         if constexpr (PAIR) {
-            NodePops<C> d;
+            Pops d;
 #pragma unroll
             for (int p = 0; p < WORDS; ++p) {
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    const int a = kPairMember[p][h];
+                    const int a = LY::member(p, h);
                     const E x = pair_half<E>(n.w[p], h);
                     if (a < 19) {
                         d.e[a] = ST::dec(x);
-                    } else if (a < 26) {
+                    } else if (a < LY::kPop) {
                         d.r[a - 19] = ST::dec(x);
                     } else if constexpr (REF_IN_PAIR) {
                         const C ref = ST::rdec(__builtin_bit_cast(typename ST::R, x));
-                        if (a == 26) d.br = ref;
+                        if (a == LY::kPop) d.br = ref;
                         else d.bt = ref;
                     }
                 }
@@ -682,7 +732,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
 #pragma unroll
             for (int a = 0; a < 19; ++a) n.e[a] = ST::dec(io.load(a, row * NS, zoff * NS));
 #pragma unroll
-            for (int a = 0; a < 7; ++a) n.r[a] = ST::dec(io.load(G0 + a, row * NS, zoff * NS));
+            for (int a = 0; a < QT; ++a) n.r[a] = ST::dec(io.load(G0 + a, row * NS, zoff * NS));
             if constexpr (DEV) {
                 n.br = ST::rdec(io.load_ref(0, row * RSZ, zoff * RSZ));
                 n.bt = ST::rdec(io.load_ref(1, row * RSZ, zoff * RSZ));
@@ -700,18 +750,18 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     };
 
     // rho = rho_r + sum e / K and T = T_r + sum r / K of a loaded node.
-    auto node_rho = [&](const NodePops<C> &n) -> C {
+    auto node_rho = [&](const Pops &n) -> C {
         if constexpr (DEV) return fmad(sum19(n.e), IK, n.br);
         else return sum19(n.e);
     };
-    auto node_T = [&](const NodePops<C> &n) -> C {
-        if constexpr (DEV) return fmad(sum7(n.r), IK, n.bt);
-        else return sum7(n.r);
+    auto node_T = [&](const Pops &n) -> C {
+        if constexpr (DEV) return fmad(sum_T<QT>(n.r), IK, n.bt);
+        else return sum_T<QT>(n.r);
     };
     // rho, T, psi (and the rounded references) of a loaded plane, tile node
     // and halo node, into LDS slot `slot`.
     auto plane_moments = [&](int slot, const Node &kraw, const Node &hraw, C &krho, C &kT, C &kpsi) {
-        const NodePops<C> k = decode(kraw);
+        const Pops k = decode(kraw);
         const C rho = node_rho(k), T = node_T(k);
         const C p2 = psi_squared(P, rho, T);
         // Unstable node (rho <= 0, psi^2 < 0 or NaN): one flag update per wave.
@@ -727,7 +777,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         kT = T;
         kpsi = psi;
         if (has_halo) {
-            const NodePops<C> h = decode(hraw);
+            const Pops h = decode(hraw);
             const C hr = node_rho(h), hT = node_T(h);
             const C hp2 = psi_squared(P, hr, hT);
             s_psi[slot][hli] = Num<C>::sqrt(hp2 > C(0) ? hp2 : C(0));
@@ -755,7 +805,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     // quantities (moments, equilibria, sources, post-collision values) are
     // carried K-scaled, so the stored values convert without a multiply.
     auto collide_stream = [&](int z, int s, const Node &ndraw, C rho, C T, C psi) {
-        const NodePops<C> nd = decode(ndraw);
+        const Pops nd = decode(ndraw);
         const int sm = (s + 3) & 3, s0 = s & 3, sp = (s + 1) & 3;
         const int sl[3] = {sm, s0, sp};
         // Eq. (7) and the isotropic gradient: omega(1) = 1/6, omega(2) = 1/12.
@@ -853,8 +903,14 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         C fs[19];  // K (f* - w rho)
         populations19(ms, fs);
 
-        // ---- D3Q7 thermal lattice ----
-        C gs[7];  // K (g+ - w T_emit)
+        // ---- temperature lattice ----
+        // Equilibrium weight of g_a: Eq. (22) on D3Q7, the standard D3Q19
+        // weights (the same as those of f) on D3Q19.
+        auto wg = [&](int a) -> C {
+            if constexpr (QT == 7) return a == 0 ? P.wT0 : P.wT1;
+            else return C(w19(a));
+        };
+        C gs[QT];  // K (g+ - w T_emit)
         const unsigned own = (unsigned)z * plane + irow;
         // Constant-temperature boundary (Sec. IV A): the outer layer of nodes
         // is a reservoir at T_shell.  It emits w T_shell without collision,
@@ -877,45 +933,70 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         const C T_emit = own_shell ? P.T_shell : T;
         if (own_shell) {
 #pragma unroll
-            for (int a = 0; a < 7; ++a) gs[a] = C(0);
+            for (int a = 0; a < QT; ++a) gs[a] = C(0);
         } else if (P.thermal) {
             // Eq. (48): local velocity divergence (pre-collision m_4).
             const C divu = fmad(P.divu_b, S4, -fmad(P.divu_a, m[4] - meq[4], C(2) * Fu)) * (C(1.5) * inv_rhoK);
-            // Eq. (38): n = N g (the reference part w T_r cancels from n1..n3, n5, n6)
-            const C n1 = nd.r[1] - nd.r[2], n2 = nd.r[3] - nd.r[4], n3 = nd.r[5] - nd.r[6];
-            const C a12 = nd.r[1] + nd.r[2], a34 = nd.r[3] + nd.r[4], a56 = nd.r[5] + nd.r[6];
-            const C n5 = a12 - a34, n6 = a12 - a56;
+            // First moments sum e g (the reference part w T_r cancels): n1..n3
+            // of Eq. (38) on D3Q7, the same sums over the 19 velocities on D3Q19.
+            C n1, n2, n3, n5 = C(0), n6 = C(0);
+            if constexpr (QT == 7) {
+                n1 = nd.r[1] - nd.r[2];
+                n2 = nd.r[3] - nd.r[4];
+                n3 = nd.r[5] - nd.r[6];
+                const C a12 = nd.r[1] + nd.r[2], a34 = nd.r[3] + nd.r[4], a56 = nd.r[5] + nd.r[6];
+                n5 = a12 - a34;
+                n6 = a12 - a56;
+            } else {
+                C mt[19];
+                moments19<C, false>(nd.r, mt);
+                n1 = mt[1];
+                n2 = mt[2];
+                n3 = mt[3];
+            }
             const C chi = P.kappa_mode ? P.kappa : P.kappa * inv_rho * P.inv_cV;
             const C inv_vsT = Num<C>::rcp(fmad(chi, P.inv_csT2, C(0.5)));
-            // Eq. (45): local temperature gradient (n is K-scaled).
+            // Eq. (45) (D3Q7 MRT) or Eq. (36) (BGK, tau_g = varsigma_T): local
+            // temperature gradient (n is K-scaled).
             const C kgr = -inv_vsT * (P.inv_csT2 * IK);
             const C dTx = kgr * n1, dTy = kgr * n2, dTz = kgr * n3;
             // Eq. (18) with (dp/dT)_rho = rho R/(1 - b rho), constant c_V.
             const C cr = chi * inv_rho;
             const C adv = fmad(fmad(cr, grx, -ux), dTx, fmad(fmad(cr, gry, -uy), dTy, fmad(cr, grz, -uz) * dTz));
             const C phis = fmad(-T * P.R * P.inv_cV, Num<C>::rcp(fmad(-P.b, rho, C(1))) * divu, adv);
-            // Eq. (39) with Eq. (42)-(43); n4 is carried as its deviation
-            // n4 - d T = (1 - d) T - g0 = w0 (T - T_r) - (g0 - w0 T_r).
-            const C keep = C(1) - inv_vsT;
-            const C s1 = n1 * keep, s2 = n2 * keep, s3 = n3 * keep;
-            // The BGK collision of Eq. (19) is the MRT one with every rate 1/tau_g = 1/varsigma_T.
-            const C gq = P.thermal_bgk ? inv_vsT : P.gam_q, gp = P.thermal_bgk ? inv_vsT : P.gam_pi;
-            const C s4 = fmad(K * P.wT0, T - nd.bt, -nd.r[0]) * (C(1) - gq);
-            const C s5 = n5 * (C(1) - gp), s6 = n6 * (C(1) - gp);
             // Eqs. (23)-(24): Q = w (1.5 phi_s - 0.5 phi_s(t-1))
             C *phi_own = A.phi + own;
             const C qs = fmad(C(1.5), phis, C(-0.5) * *phi_own);
-            const C Q0 = (K * P.wT0) * qs, Q1 = (K * P.wT1) * qs;
-            // Eq. (40)-(41): g+ = N^-1 n* + Q = w T + N^-1 (n* - n_eq) + Q
-            const C c456 = (s4 + s5 + s6) * C(1.0 / 6.0);
-            const C c3 = (s4 - C(2) * s5 + s6) * C(1.0 / 6.0), c5 = (s4 + s5 - C(2) * s6) * C(1.0 / 6.0);
-            gs[0] = Q0 - s4;
-            gs[1] = fmad(C(0.5), s1, c456) + Q1;
-            gs[2] = fmad(C(-0.5), s1, c456) + Q1;
-            gs[3] = fmad(C(0.5), s2, c3) + Q1;
-            gs[4] = fmad(C(-0.5), s2, c3) + Q1;
-            gs[5] = fmad(C(0.5), s3, c5) + Q1;
-            gs[6] = fmad(C(-0.5), s3, c5) + Q1;
+            const C keep = C(1) - inv_vsT;
+            if constexpr (QT == 7) {
+                // Eq. (39) with Eq. (42)-(43); n4 is carried as its deviation
+                // n4 - d T = (1 - d) T - g0 = w0 (T - T_r) - (g0 - w0 T_r).
+                const C s1 = n1 * keep, s2 = n2 * keep, s3 = n3 * keep;
+                // The BGK collision of Eq. (19) is the MRT one with every rate 1/tau_g = 1/varsigma_T.
+                const C gq = P.thermal_bgk ? inv_vsT : P.gam_q, gp = P.thermal_bgk ? inv_vsT : P.gam_pi;
+                const C s4 = fmad(K * P.wT0, T - nd.bt, -nd.r[0]) * (C(1) - gq);
+                const C s5 = n5 * (C(1) - gp), s6 = n6 * (C(1) - gp);
+                const C Q0 = (K * P.wT0) * qs, Q1 = (K * P.wT1) * qs;
+                // Eq. (40)-(41): g+ = N^-1 n* + Q = w T + N^-1 (n* - n_eq) + Q
+                const C c456 = (s4 + s5 + s6) * C(1.0 / 6.0);
+                const C c3 = (s4 - C(2) * s5 + s6) * C(1.0 / 6.0), c5 = (s4 + s5 - C(2) * s6) * C(1.0 / 6.0);
+                gs[0] = Q0 - s4;
+                gs[1] = fmad(C(0.5), s1, c456) + Q1;
+                gs[2] = fmad(C(-0.5), s1, c456) + Q1;
+                gs[3] = fmad(C(0.5), s2, c3) + Q1;
+                gs[4] = fmad(C(-0.5), s2, c3) + Q1;
+                gs[5] = fmad(C(0.5), s3, c5) + Q1;
+                gs[6] = fmad(C(-0.5), s3, c5) + Q1;
+            } else {
+                // Eq. (19) with g_eq = w T: K (g+ - w T) = K (g - w T)(1 - 1/tau_g) + K w Q,
+                // where K (g - w T) = r - K w (T - T_r) (T_r = 0 for plain storage).
+                const C dT = T - nd.bt;
+#pragma unroll
+                for (int a = 0; a < 19; ++a) {
+                    const C wK = C(K * w19(a));
+                    gs[a] = fmad(fmad(-wK, dT, nd.r[a]), keep, wK * qs);
+                }
+            }
             *phi_own = phis;
         }
 
@@ -964,25 +1045,33 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
                 return ST::enc(fa[a]);
             }
         };
-        // D3Q7: g+ = w T_emit + gs; the deviation formats encode against the
+        // g+ = w T_emit + gs; the deviation formats encode against the
         // destination's T_r as above.  A destination in the reservoir layer
-        // receives w T_shell.
-        const C wT = P.wT1 * T_emit, wT0 = T_emit - C(6) * wT;
-        const C wS = P.wT1 * P.T_shell, wS0 = P.T_shell - C(6) * wS;
-        C ga[7];
+        // receives w T_shell.  Plain storage forms the rest part as T minus
+        // the moving ones, so that the weights sum to 1 exactly.
+        auto wtimes = [&](int a, C t) -> C {
+            if constexpr (QT == 7) {
+                const C w1 = P.wT1 * t;
+                return a == 0 ? t - C(6) * w1 : w1;
+            } else {
+                const C t1 = t * C(1.0 / 18.0), t2 = t * C(1.0 / 36.0);
+                return a == 0 ? t - fmad(C(6), t1, C(12) * t2) : (a < 7 ? t1 : t2);
+            }
+        };
+        C ga[QT];
 #pragma unroll
-        for (int a = 0; a < 7; ++a) {
-            if constexpr (DEV) ga[a] = fmad(K * (a == 0 ? P.wT0 : P.wT1), T_emit - own_tref, gs[a]);
-            else ga[a] = (a == 0 ? wT0 : wT) + gs[a];
+        for (int a = 0; a < QT; ++a) {
+            if constexpr (DEV) ga[a] = fmad(K * wg(a), T_emit - own_tref, gs[a]);
+            else ga[a] = wtimes(a, T_emit) + gs[a];
         }
         auto gval = [&](int a, int slot, int dx, int dy, bool to_shell) -> C {
             if constexpr (DEV) {
                 const C bd = s_tref[slot][li + dy * EX + dx];
-                const C wK = K * (a == 0 ? P.wT0 : P.wT1);
+                const C wK = K * wg(a);
                 if (to_shell) return wK * (P.T_shell - bd);
                 return fmad(wK, own_tref - bd, ga[a]);
             } else {
-                if (to_shell) return a == 0 ? wS0 : wS;
+                if (to_shell) return wtimes(a, P.T_shell);
                 return ga[a];
             }
         };
@@ -990,23 +1079,23 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         if constexpr (PAIR && !WALLS) {
           if (P.thermal) {
             stored = true;
-            // f_a and g_a of the same velocity (a = 0..6) go to the same
+            // f_a and g_a of the same velocity (a < QT) go to the same
             // neighbour and share a word of the paired layout: one store.
             auto word = [](E lo, E hi) { return pack_pair<E>(lo, hi); };
 #pragma unroll
-            for (int a = 0; a < 7; ++a) {
+            for (int a = 0; a < QT; ++a) {
                 const int ex = kE19X[a], ey = kE19Y[a], ez = kE19Z[a];
                 const bool to_shell = xs[ex + 1] || ys[ey + 1] || zs[ez + 1];
-                io.store_pair(kPairOf[a], Yo[ey + 1] + Xo[ex + 1], Zo[ez + 1],
+                io.store_pair(LY::pair_of(a), Yo[ey + 1] + Xo[ex + 1], Zo[ez + 1],
                               word(fval(a, sl[ez + 1], ex, ey), ST::enc(gval(a, sl[ez + 1], ex, ey, to_shell))));
             }
 #pragma unroll
-            for (int a = 7; a < 19; ++a) {
+            for (int a = QT; a < 19; ++a) {
                 const int ex = kE19X[a], ey = kE19Y[a], ez = kE19Z[a];
                 io.store(a, Yo[ey + 1] + Xo[ex + 1], Zo[ez + 1], fval(a, sl[ez + 1], ex, ey));
             }
             if constexpr (REF_IN_PAIR) {
-                io.store_pair(kPairOf[kPopPlanes], rowb, Zc,
+                io.store_pair(LY::pair_of(LY::kPop), rowb, Zc,
                               word(__builtin_bit_cast(E, ST::renc(rho)), __builtin_bit_cast(E, ST::renc(T))));
             } else if constexpr (DEV) {
                 io.store_ref(0, irow * RU, (unsigned)z * plane * RU, ST::renc(rho));
@@ -1032,15 +1121,15 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
             }
             if (P.thermal) {
     #pragma unroll
-                for (int a = 0; a < 7; ++a) {
-                    const int ex = kE7X[a], ey = kE7Y[a], ez = kE7Z[a];
+                for (int a = 0; a < QT; ++a) {
+                    const int ex = kE19X[a], ey = kE19Y[a], ez = kE19Z[a];  // Eq. (21) is the first 7 of Eq. (2)
                     if (WALLS) {
                         // Eq. (51): g_opp(x_b) = -g+_a(x_b) + 2 w T_w, into the own node
                         const bool bottom = ez < 0 && z == 0, top = ez > 0 && z == nz - 1;
                         if (bottom || top) {
                             const C Tw = bottom ? T_bottom : (C)P.T_top;
-                            const C v = DEV ? fmad(K * P.wT1, C(2) * Tw - T - own_tref, -gs[a])
-                                            : fmad(C(2) * P.wT1, Tw, -ga[a]);
+                            const C v = DEV ? fmad(K * wg(a), C(2) * Tw - T - own_tref, -gs[a])
+                                            : fmad(C(2) * wg(a), Tw, -ga[a]);
                             io.store(G0 + opposite(a), rowb, Zc, ST::enc(v));
                             continue;
                         }
@@ -1051,8 +1140,8 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
             } else {
                 // temperature held fixed: g stays at the node (re-encoded against the new reference)
     #pragma unroll
-                for (int a = 0; a < 7; ++a) {
-                    const C v = DEV ? fmad(K * (a == 0 ? P.wT0 : P.wT1), nd.bt - own_tref, nd.r[a]) : nd.r[a];
+                for (int a = 0; a < QT; ++a) {
+                    const C v = DEV ? fmad(K * wg(a), nd.bt - own_tref, nd.r[a]) : nd.r[a];
                     io.store(G0 + a, rowb, Zc, ST::enc(v));
                 }
             }
@@ -1179,12 +1268,13 @@ __global__ void __launch_bounds__(TX *TY) k_step_batch(const StepArgs<ST> *__res
 
 template <typename ST>
 struct NodeView {
+    static constexpr int QT = ST::kQT, kPopPlanes = PopLayout<QT>::kPop;
     const typename ST::T *pop;
     size_t st;
-    __device__ double e(int a, size_t i) const { return ST::ddec(pop[element_index<typename ST::T>(a, st, i)]); }
+    __device__ double e(int a, size_t i) const { return ST::ddec(pop[element_index<typename ST::T, QT>(a, st, i)]); }
     __device__ double ref(int k, size_t i) const {
         if constexpr (ST::kDev && sizeof(typename ST::R) == sizeof(typename ST::T)) {
-            return (double)ST::rdec(__builtin_bit_cast(typename ST::R, pop[element_index<typename ST::T>(kPopPlanes + k, st, i)]));
+            return (double)ST::rdec(__builtin_bit_cast(typename ST::R, pop[element_index<typename ST::T, QT>(kPopPlanes + k, st, i)]));
         } else if constexpr (ST::kDev) {
             const typename ST::R *refs = reinterpret_cast<const typename ST::R *>(pop + kPopPlanes * st);
             return (double)ST::rdec(refs[k * st + i]);
@@ -1211,23 +1301,26 @@ __global__ void __launch_bounds__(256) k_init(const double *__restrict__ stage, 
     double br = 0.0, bt = 0.0;
     using T_ = typename ST::T;
     using R_ = typename ST::R;
+    constexpr int QT = ST::kQT, NP = PopLayout<QT>::kPop;
     if constexpr (ST::kDev) {
         br = (double)ST::rdec(ST::renc((float)rho));
         bt = (double)ST::rdec(ST::renc((float)T));
         if constexpr (sizeof(R_) == sizeof(T_)) {
-            pop[element_index<T_>(kPopPlanes, st, i)] = __builtin_bit_cast(T_, ST::renc((float)rho));
-            pop[element_index<T_>(kPopPlanes + 1, st, i)] = __builtin_bit_cast(T_, ST::renc((float)T));
+            pop[element_index<T_, QT>(NP, st, i)] = __builtin_bit_cast(T_, ST::renc((float)rho));
+            pop[element_index<T_, QT>(NP + 1, st, i)] = __builtin_bit_cast(T_, ST::renc((float)T));
         } else {
-            R_ *refs = reinterpret_cast<R_ *>(pop + kPopPlanes * st);
+            R_ *refs = reinterpret_cast<R_ *>(pop + NP * st);
             refs[i] = ST::renc((float)rho);
             refs[st + i] = ST::renc((float)T);
         }
     }
 #pragma unroll
-    for (int a = 0; a < 19; ++a) pop[element_index<T_>(a, st, i)] = ST::denc(fl[a] - w19(a) * br);
-    pop[element_index<T_>(19, st, i)] = ST::denc(P.wT0 * (T - bt));
+    for (int a = 0; a < 19; ++a) pop[element_index<T_, QT>(a, st, i)] = ST::denc(fl[a] - w19(a) * br);
 #pragma unroll
-    for (int a = 1; a < 7; ++a) pop[element_index<T_>(19 + a, st, i)] = ST::denc(P.wT1 * (T - bt));
+    for (int a = 0; a < QT; ++a) {
+        const double w = QT == 7 ? (a == 0 ? P.wT0 : P.wT1) : w19(a);
+        pop[element_index<T_, QT>(19 + a, st, i)] = ST::denc(w * (T - bt));
+    }
     phi[i] = typename ST::C(0);
 }
 
@@ -1238,12 +1331,13 @@ __global__ void __launch_bounds__(256) k_macro(const typename ST::T *__restrict_
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nn) return;
     const NodeView<ST> v{pop, st};
-    double fl[19], gl[7];
+    constexpr int QT = ST::kQT;
+    double fl[19], gl[QT];
 #pragma unroll
     for (int a = 0; a < 19; ++a) fl[a] = v.e(a, i);
 #pragma unroll
-    for (int a = 0; a < 7; ++a) gl[a] = v.e(19 + a, i);
-    const double rho = v.ref(0, i) + sum19(fl), T = v.ref(1, i) + sum7(gl);
+    for (int a = 0; a < QT; ++a) gl[a] = v.e(19 + a, i);
+    const double rho = v.ref(0, i) + sum19(fl), T = v.ref(1, i) + sum_T<QT>(gl);
     const double p2 = psi_squared(P, rho, T);
     stage[i] = rho;
     stage[4 * nn + i] = T;
@@ -1294,13 +1388,14 @@ __global__ void __launch_bounds__(256) k_sum(const typename ST::T *__restrict__ 
     double r = 0.0, t = 0.0;
     if (i < nn) {
         const NodeView<ST> v{pop, st};
-        double fl[19], gl[7];
+        constexpr int QT = ST::kQT;
+        double fl[19], gl[QT];
 #pragma unroll
         for (int a = 0; a < 19; ++a) fl[a] = v.e(a, i);
 #pragma unroll
-        for (int a = 0; a < 7; ++a) gl[a] = v.e(19 + a, i);
+        for (int a = 0; a < QT; ++a) gl[a] = v.e(19 + a, i);
         r = v.ref(0, i) + sum19(fl);
-        t = v.ref(1, i) + sum7(gl);
+        t = v.ref(1, i) + sum_T<QT>(gl);
     }
     for (int o = 32; o > 0; o >>= 1) {
         r += __shfl_xor(r, o, 64);

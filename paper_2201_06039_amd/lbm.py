@@ -35,6 +35,7 @@ class LbmParams(ctypes.Structure):
         ("patch_radius", ctypes.c_double), ("T_top", ctypes.c_double),
         ("thermal", ctypes.c_int), ("storage", ctypes.c_int),
         ("bc_T_shell", ctypes.c_int), ("T_shell", ctypes.c_double), ("thermal_bgk", ctypes.c_int),
+        ("thermal_lattice", ctypes.c_int),
     ]
 
 
@@ -121,6 +122,7 @@ def make_params(params: dict, storage="f32") -> LbmParams:
     src.setdefault("bc_T_shell", 0)
     src.setdefault("T_shell", 0.0)
     src.setdefault("thermal_bgk", 0)
+    src.setdefault("thermal_lattice", 0)
     for n in names:
         if n not in src:
             raise KeyError(f"missing parameter {n!r}")

@@ -127,3 +127,25 @@ def test_batch_validation(lib):
     assert lib.lbm_batch_step(None, 1) == lbm.EINVAL
     lib.lbm_batch_destroy(None)
 
+
+
+def test_d3q19_temperature_lattice_arena_and_validation(lib):
+    """The D3Q19 temperature lattice stores 19 g planes (38 population planes
+    per copy); it takes the BGK collision, the F32, F64 and F16 formats, and
+    no batches."""
+    from paper_2201_06039_amd import lbm, workloads as W
+    p = dict(W.load("evaporation_128")["params"], thermal_lattice=1, thermal_bgk=1)
+    n = 128 ** 3
+    for fmt, es, refs, cs in (("f16", 2, 2 * 2, 4), ("f32", 4, 0, 4), ("f64", 8, 0, 8)):
+        copy = (38 * es + refs) * n
+        rest = cs * n + 6 * 8 * n
+        b = lbm.arena_bytes(p, fmt)
+        assert 2 * copy + rest <= b < 2 * copy + rest + (1 << 22), fmt
+        assert b > lbm.arena_bytes(dict(p, thermal_lattice=0), fmt)
+    for fmt in ("bf16", "f32dev"):
+        assert lbm.arena_bytes(p, fmt) == 0, fmt
+    for bad in (dict(thermal_bgk=0), dict(thermal_lattice=2), dict(thermal_lattice=-1)):
+        assert lbm.arena_bytes(dict(p, **bad)) == 0, bad
+    a = dict(W.load("static_droplet_32")["params"])
+    assert lbm.batch_arena_bytes([a, a], "f16") > 0
+    assert lbm.batch_arena_bytes([a, dict(a, thermal_lattice=1, thermal_bgk=1)], "f16") == 0

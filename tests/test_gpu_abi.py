@@ -31,12 +31,16 @@ def test_checkpoint_continuation_bitwise():
         assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("storage", ["f16", "bf16", "f32dev", "f64"])
-def test_checkpoint_continuation_bitwise_other_formats(storage):
+@pytest.mark.parametrize("storage,q19", [("f16", 0), ("bf16", 0), ("f32dev", 0), ("f64", 0), ("f16", 1),
+                                        ("f32", 1), ("f64", 1)])
+def test_checkpoint_continuation_bitwise_other_formats(storage, q19):
     """The raw state of every format (FP16 and FP32 reference planes for the
-    deviation formats) round-trips through get_state/set_state."""
+    deviation formats; 19 g planes for the D3Q19 temperature lattice)
+    round-trips through get_state/set_state."""
     w = workload("evaporation_128", nx=24, ny=20, nz=18, radius=5.0)
-    print(f"checkpoint {storage}", flush=True)
+    if q19:
+        w["params"].update(thermal_lattice=1, thermal_bgk=1)
+    print(f"checkpoint {storage} d3q19-temperature={q19}", flush=True)
     fields = W.fields(w)
     a = _lattice(w, storage)
     a.init_fields(*fields)
@@ -123,11 +127,15 @@ def test_set_state_rejects_wrong_size_and_header():
 # rounded, and the roundings of a node's 19 values do not sum to zero.  The
 # mass bar is 2^-p of the rounding-error walk over 200 steps for p-bit storage
 # rounded to a decade: 1e-6 (f32dev), 1e-5 (f16), 1e-4 (bf16).
-@pytest.mark.parametrize("storage,tol", [("f64", 1e-13), ("f32", 1e-6), ("f32dev", 1e-6), ("f16", 1e-5),
-                                         ("bf16", 1e-4)])
-def test_mass_conservation_and_reduce(storage, tol):
-    """Sum rho is conserved on a periodic grid; lbm_reduce matches the oracle."""
+@pytest.mark.parametrize("storage,tol,q19", [("f64", 1e-13, 0), ("f32", 1e-6, 0), ("f32dev", 1e-6, 0),
+                                             ("f16", 1e-5, 0), ("bf16", 1e-4, 0), ("f64", 1e-13, 1),
+                                             ("f16", 1e-5, 1)])
+def test_mass_conservation_and_reduce(storage, tol, q19):
+    """Sum rho is conserved on a periodic grid; lbm_reduce matches the oracle
+    (sum T over the 7 or 19 temperature populations)."""
     w = workload("evaporation_128", nx=40, ny=40, nz=40, radius=9.0)
+    if q19:
+        w["params"].update(thermal_lattice=1, thermal_bgk=1)
     fields = W.fields(w)
     lat = _lattice(w, storage)
     lat.init_fields(*fields)
