@@ -55,6 +55,8 @@ typedef struct orc_params {
     double T_shell;        /* temperature of that layer */
     int thermal_bgk;       /* 1: BGK temperature collision of Eq. (19) instead of the MRT one */
     int thermal_lattice;   /* 0: D3Q7 (Sec. III B); 1: D3Q19 with the standard weights, BGK only */
+    int divu_mode;         /* 0: Eq. (48) at every node; 1: isotropic finite differences of u at
+                              interior nodes, Eq. (48) at the layers next to a wall or the open top */
 } orc_params;
 
 typedef struct orc_sim {
@@ -73,6 +75,7 @@ typedef struct orc_sim {
     double *fn, *gn;            /* streamed state for t+1 */
     double *rho, *T, *psi;
     double *Fm, *grho;          /* 3 components, component-major */
+    double *uall;               /* u of Eq. (10) at every node (divu_mode 1), component-major */
     double rho_ave;             /* average density used by the next step's buoyancy */
     int status;
 } orc_sim;
@@ -413,6 +416,16 @@ static void pass_collide(orc_sim *s) {
     const int QT = s->QT;
     double lam[Q19];
     relaxation_rates(p, lam);
+    if (p->divu_mode == 1) {
+        /* u(t) of Eq. (10) at every node, for the finite-difference divergence. */
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < nn; ++i) {
+            double F[3], Fm[3], u[3];
+            total_force(s, i, F, Fm);
+            velocity(s, i, F, u);
+            for (int c = 0; c < 3; ++c) s->uall[c * nn + i] = u[c];
+        }
+    }
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < nn; ++i) {
         const double rho = s->rho[i];
@@ -450,8 +463,23 @@ static void pass_collide(orc_sim *s) {
         /* Eq. (48): local velocity divergence from the non-equilibrium part
          * of m_4 (reading: applied at every node, pre-collision m_4). */
         const double Fu = F[0] * u[0] + F[1] * u[1] + F[2] * u[2];
-        const double divu = (-(m[4] - meq[4]) / (p->tau_e * dt) + (1.0 - 1.0 / (2.0 * p->tau_e)) * S[4] - 2.0 * Fu)
-                            / (2.0 * rho * cs2);
+        double divu = (-(m[4] - meq[4]) / (p->tau_e * dt) + (1.0 - 1.0 / (2.0 * p->tau_e)) * S[4] - 2.0 * Fu)
+                      / (2.0 * rho * cs2);
+        if (p->divu_mode == 1) {
+            /* The practice Eq. (48) replaces (Sec. III C): the isotropic
+             * finite-difference divergence sum omega(|e|^2) e . u(x + e) of
+             * u(t) at interior nodes; the layers next to a wall or the open
+             * top keep Eq. (48). */
+            const int x = (int)(i % p->nx), y = (int)((i / p->nx) % p->ny), z = (int)(i / ((long)p->nx * p->ny));
+            if (p->bc_z == 0 || (z > 0 && z < p->nz - 1)) {
+                double acc = 0.0;
+                for (int a = 1; a < Q19; ++a) {
+                    const long j = stencil_neighbour(p, x, y, z, E19[a]);
+                    for (int c = 0; c < 3; ++c) acc += s->omega[a] * E19[a][c] * s->uall[c * nn + j];
+                }
+                divu = acc;
+            }
+        }
 
         const double T = s->T[i];
         /* chi = lambda/(rho cV) (constant lambda) or given; chi = (vs_T - 0.5) c_sT^2 dt. */
@@ -604,7 +632,7 @@ void orc_destroy(orc_sim *s) {
     if (!s) return;
     free(s->f); free(s->g); free(s->phi_prev); free(s->fs); free(s->gp);
     free(s->fn); free(s->gn); free(s->rho); free(s->T); free(s->psi);
-    free(s->Fm); free(s->grho);
+    free(s->Fm); free(s->grho); free(s->uall);
     free(s);
 }
 
@@ -617,6 +645,7 @@ int orc_create(const orc_params *p, orc_sim **out) {
     /* Reading: the paper gives relaxation rates for the D3Q7 moments only,
      * so the D3Q19 temperature lattice takes the BGK collision. */
     if (p->thermal_lattice != 0 && (p->thermal_lattice != 1 || !p->thermal_bgk)) return ORC_EINVAL;
+    if (p->divu_mode != 0 && p->divu_mode != 1) return ORC_EINVAL;
     if (p->tau_e <= 0.5 || p->tau_v <= 0.5 || p->tau_q <= 0.5 || p->tau_pi <= 0.5) return ORC_EINVAL;
     if (p->vs_q <= 0.5 || p->vs_pi <= 0.5 || p->G == 0.0 || p->cV <= 0.0) return ORC_EINVAL;
     orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
@@ -637,8 +666,9 @@ int orc_create(const orc_params *p, orc_sim **out) {
     s->psi = calloc(nn, sizeof(double));
     s->Fm = calloc(3 * nn, sizeof(double));
     s->grho = calloc(3 * nn, sizeof(double));
+    s->uall = calloc(3 * nn, sizeof(double));
     if (!s->f || !s->fs || !s->fn || !s->g || !s->gp || !s->gn || !s->phi_prev || !s->rho || !s->T ||
-        !s->psi || !s->Fm || !s->grho) {
+        !s->psi || !s->Fm || !s->grho || !s->uall) {
         orc_destroy(s);
         return ORC_ENOMEM;
     }

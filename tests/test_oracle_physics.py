@@ -651,3 +651,69 @@ def test_d3q7_and_d3q19_temperature_lattices_agree(oracle_lib):
     assert scale > 0.02 * Tc
     assert np.abs(dT19 - dT7).max() < 0.05 * scale
     assert np.abs(out["q19"][0] - out["q7"][0]).max() < 1e-2 * rl
+
+
+# --------------------------------------------------------------------------
+# Finite-difference velocity divergence (divu_mode = 1): the practice that
+# Eq. (48) replaces (Sec. III C) -- isotropic differences of u at interior
+# nodes, Eq. (48) at the layers next to a wall or the open top.
+# --------------------------------------------------------------------------
+
+def _divergence_first_step(oracle_lib, mode, walls):
+    """One step from f = f_eq(rho, u) with u = U sin(kx) x, uniform rho and T,
+    a = b = 0 (no force: psi is uniform).  At t = 0 the non-equilibrium m_4
+    is zero, so Eq. (48) gives div u = 0, and the finite-difference divergence
+    is sum omega e.u(x+e) = (u(x+1) - u(x-1))/2 = U sin(k) cos(kx).  With
+    grad T = 0 the temperature change is 1.5 phi_s streamed with the D3Q7
+    weights, phi_s = -T R/c_V div u (Eq. (18), b = 0)."""
+    L, U, T0, cV, d = 16, 1e-3, 0.1, 5.0, 0.95
+    nz = 6 if walls else 1
+    k = 2 * np.pi / L
+    x = np.arange(L)
+    ux = np.broadcast_to(U * np.sin(k * x), (nz, 1, L)).copy()
+    ones = np.ones_like(ux)
+    kw = dict(bc_z=1, T_wall_patch=T0, T_wall=T0, T_top=T0, patch_radius=0.0) if walls else {}
+    s = oracle_lib.Sim(nx=L, ny=1, nz=nz, a=0.0, b=0.0, R=1.0, cV=cV, d=d, kappa_mode=1, kappa=0.05,
+                       divu_mode=mode, **kw)
+    s.init_fields(ones, ux, 0 * ones, 0 * ones, T0 * ones)
+    s.step(1)
+    T1 = s.rho_u_T()[4]
+    phi = -T0 * 1.0 / cV * U * np.sin(k) * np.cos(k * x)
+    return T1, phi, T0, d, k
+
+
+def test_fd_divergence_closed_form_first_step(oracle_lib):
+    T1, phi, T0, d, k = _divergence_first_step(oracle_lib, 1, False)
+    expect = T0 + 1.5 * phi * (1.0 - d / 3.0 * (1.0 - np.cos(k)))
+    np.testing.assert_allclose(T1.reshape(-1), expect, rtol=0, atol=1e-15)
+    T1, phi, T0, d, k = _divergence_first_step(oracle_lib, 0, False)
+    np.testing.assert_allclose(T1.reshape(-1), T0, rtol=0, atol=1e-15)
+
+
+def test_fd_divergence_keeps_eq48_at_the_wall_layers(oracle_lib):
+    """With walls the bottom and top layers use Eq. (48) (zero at t = 0); the
+    only source reaching them in the first step is the one streamed from the
+    interior layer next to them along e_z, weight d/6."""
+    T1, phi, T0, d, k = _divergence_first_step(oracle_lib, 1, True)
+    for z in (0, T1.shape[0] - 1):
+        np.testing.assert_allclose(T1[z, 0], T0 + 1.5 * d / 6.0 * phi, rtol=0, atol=1e-15)
+    # an interior layer between two interior layers sees the full stencil
+    np.testing.assert_allclose(T1[2, 0], T0 + 1.5 * phi * (1.0 - d / 3.0 * (1.0 - np.cos(k))), rtol=0, atol=1e-15)
+
+
+def test_fd_divergence_compression_heating(oracle_lib):
+    """The finite-difference divergence drives the same compression heating
+    as Eq. (48): dT = T R/(rho c_V) d rho for a small acoustic wave."""
+    L = 64
+    x = np.arange(L)
+    T0, rho0, cV, Rg = 0.1, 1.0, 5.0, 1.0
+    rho = (rho0 + 1e-3 * np.sin(2 * np.pi * x / L)).reshape(1, 1, L)
+    ones = np.ones_like(rho)
+    s = oracle_lib.Sim(nx=L, ny=1, nz=1, a=0.0, b=0.0, R=Rg, cV=cV, kappa_mode=1, kappa=0.001, divu_mode=1)
+    s.init_fields(rho, 0 * ones, 0 * ones, 0 * ones, T0 * ones)
+    r0 = s.rho_u_T()[0].reshape(L).copy()
+    s.step(100)
+    r, _, _, _, T = s.rho_u_T()
+    dr = r.reshape(L) - r0
+    dT = T.reshape(L) - T0
+    assert (dr * dT).sum() / (dr * dr).sum() == pytest.approx(T0 * Rg / (rho0 * cV), rel=2e-2)
