@@ -2,7 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                     [--storage f16|f32|f64|bf16|f32dev] [--compare f32|none]
-                    [--thermal-lattice d3q7|d3q19] [--tile TXxTY] [--chunk CZ]
+                    [--thermal-lattice d3q7|d3q19] [--divu local|fd] [--tile TXxTY] [--chunk CZ]
                     [--no-precision] [--no-batch] [--no-lattice-comparison] [--no-cpu-baseline]
 
 One step = one fused time step of the whole grid (both lattices, streaming and
@@ -199,6 +199,26 @@ def lattice_comparison(lbm, p, fields, steps, warmup, storages=("f16", "f32")):
     return out
 
 
+def divergence_comparison(lbm, p, fields, steps, warmup, storages=("f16", "f32")):
+    """The step with div u of Eq. (48) at every node against the practice it
+    replaces, isotropic finite differences of u(t) at interior nodes, which
+    needs u at every node before the step (here two more passes over the
+    state, into FP64 staging planes)."""
+    nn = p["nx"] * p["ny"] * p["nz"]
+    out = {}
+    for storage in storages:
+        row = {}
+        for name, mode in (("local_eq48", 0), ("finite_difference", 1)):
+            ms, launch, launches = timed_run(lbm, dict(p, divu_mode=mode), fields, storage, steps, warmup)
+            row[name] = {"MLUPS": round(nn * steps / (ms / 1e3) / 1e6, 2), "ms_per_step": round(ms / steps, 5),
+                         "launches_per_step": launches, "tile": [launch["tile_x"], launch["tile_y"]],
+                         "chunk_z": launch["chunk_z"]}
+            print(f"# divergence {name} {storage}: {ms / steps:.5f} ms/step", file=sys.stderr, flush=True)
+        row["speedup_of_local"] = round(row["finite_difference"]["ms_per_step"] / row["local_eq48"]["ms_per_step"], 3)
+        out[storage] = row
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,6 +240,8 @@ def main():
                     help="fixed batch launch (tile, chunk, workgroups) instead of the autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lattice-comparison", action="store_true")
+    ap.add_argument("--divu", default="local", choices=["local", "fd"],
+                    help="velocity divergence of the timed step: Eq. (48) or finite differences")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="only run 20 plain device-to-device copies of MB megabytes (to calibrate the "
                          "FETCH_SIZE/WRITE_SIZE counters against a kernel of known traffic) and exit")
@@ -265,6 +287,9 @@ def main():
         if args.storage not in BYTES_PER_LUP_Q19T:
             ap.error(f"the D3Q19 temperature lattice is built for {sorted(BYTES_PER_LUP_Q19T)}")
         p.update(thermal_lattice=1, thermal_bgk=1)
+    fd = args.divu == "fd"
+    if fd:
+        p["divu_mode"] = 1
     nn = p["nx"] * p["ny"] * p["nz"]
 
     print(f"# workload {args.workload} {p['nx']}x{p['ny']}x{p['nz']} storage {args.storage}", file=sys.stderr,
@@ -293,6 +318,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": [p["nx"], p["ny"], p["nz"]], "storage": args.storage,
                    "temperature_lattice": args.thermal_lattice.upper() + (" BGK" if q19t else " MRT"),
+                   "velocity_divergence": "finite differences" if fd else "Eq. (48)",
                    "tile": [launch["tile_x"], launch["tile_y"]], "chunk_z": launch["chunk_z"],
                    "workgroups": launch["workgroups"], "launches_per_step": launches},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -310,15 +336,16 @@ def main():
                           "bytes_per_lup": bytes_per_lup(args.compare, q19t),
                           "tile": [launch2["tile_x"], launch2["tile_y"]], "chunk_z": launch2["chunk_z"],
                           "speedup_of_storage": round(ms2 / ms, 3)}
-    if not args.no_lattice_comparison and not q19t:
+    if not args.no_lattice_comparison and not q19t and not fd:
         out["temperature_lattice_comparison"] = lattice_comparison(lbm, p, fields, max(1, args.steps // 2),
                                                                    args.warmup)
-    if not args.no_precision and not q19t:
+        out["divergence_comparison"] = divergence_comparison(lbm, p, fields, max(1, args.steps // 4), args.warmup)
+    if not args.no_precision and not q19t and not fd:
         errs = precision_errors(args.storage)
         print(f"# precision of {args.storage}: {errs}", file=sys.stderr, flush=True)
         out["precision"] = {"storage": args.storage, "reference": "FP64 oracle", "bound": PRECISION_BOUND,
                             "relative_errors": errs, "within_bound": max(errs.values()) <= PRECISION_BOUND}
-    if not args.no_batch and not q19t:
+    if not args.no_batch and not q19t and not fd:
         bl = tuple(int(v) for v in args.batch_launch.split("x")) if args.batch_launch else None
         out["batch"] = batch_run(args.storage if args.storage != "f64" else "f32", args.batch_steps, 10, launch=bl)
         print(f"# batch: {out['batch']}", file=sys.stderr, flush=True)

@@ -64,6 +64,15 @@ extern "C" {
                             /* (thermal_bgk = 1); storage F32, F64 or F16; not in */
                             /* batches                                            */
 
+/* Velocity divergence in the source term of Eq. (18) (Sec. III C). */
+#define LBM_DIVU_LOCAL 0 /* Eq. (48) at every node, from the non-equilibrium m_4 */
+#define LBM_DIVU_FD 1    /* the practice Eq. (48) replaces: isotropic finite     */
+                         /* differences sum omega(|e|^2) e . u(x + e) of u(t) of */
+                         /* Eq. (10) at interior nodes, Eq. (48) at the layers   */
+                         /* next to a wall or the open top.  Each step first     */
+                         /* computes u at every node (two more launches into the */
+                         /* FP64 staging planes); not in batches                 */
+
 /* Storage format of the populations.
  *   F32, F64: the populations f, g themselves; arithmetic in the same type.
  *   F16, BF16, F32_DEV: deviations from the rest equilibrium of a per-node
@@ -121,6 +130,7 @@ typedef struct lbm_params {
                              /* grad T from Eq. (36)                           */
     int thermal_lattice;     /* LBM_THERMAL_*; D3Q19 stores 19 g planes        */
                              /* instead of 7 (38 population planes, not 26)   */
+    int divu_mode;           /* LBM_DIVU_*                                     */
 } lbm_params;
 
 typedef struct lbm_handle lbm_handle;
@@ -175,12 +185,14 @@ int lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes);
  * nodes per workgroup marching over chunk_z planes.  Supported tiles:
  * 64x4, 32x8, 64x8, 32x16, 128x4 (F64 storage: 64x4 and 32x8 only);
  * chunk_z >= 1 (values above nz are clamped to nz).  EINVAL otherwise.
+ * With LBM_DIVU_FD a tile whose LDS (static + the u ring) exceeds the
+ * device's per-workgroup limit makes lbm_step() return EINVAL.
  * The result of a step does not depend on the launch shape. */
 int lbm_set_launch(lbm_handle *h, int tile_x, int tile_y, int chunk_z);
 int lbm_get_launch(const lbm_handle *h, int *tile_x, int *tile_y, int *chunk_z, int *workgroups);
 
-/* Number of kernel launches lbm_step() enqueues per time step (1, or 2 when
- * gravity needs the rho_ave reduction). */
+/* Number of kernel launches lbm_step() enqueues per time step: 1, plus 1
+ * when gravity needs the rho_ave reduction, plus 2 with LBM_DIVU_FD. */
 int lbm_launches_per_step(const lbm_handle *h);
 
 /* Release host resources; the arena stays with the caller.  NULL-safe. */

@@ -74,6 +74,7 @@ bool valid_params(const lbm_params *p) {
     // The paper gives relaxation rates for the D3Q7 moments only: the D3Q19
     // temperature lattice takes the BGK collision.
     if (p->thermal_lattice != LBM_THERMAL_D3Q7 && p->thermal_lattice != LBM_THERMAL_D3Q19) return false;
+    if (p->divu_mode != LBM_DIVU_LOCAL && p->divu_mode != LBM_DIVU_FD) return false;
     if (p->thermal_lattice == LBM_THERMAL_D3Q19 &&
         (!p->thermal_bgk || p->storage == LBM_STORE_BF16 || p->storage == LBM_STORE_F32_DEV))
         return false;
@@ -192,6 +193,7 @@ lbm::Phys<C> make_phys(const lbm_params *p) {
     P.thermal = p->thermal;
     P.shell = p->bc_T_shell;
     P.thermal_bgk = p->thermal_bgk;
+    P.divu_fd = p->divu_mode == LBM_DIVU_FD;
     P.T_shell = (C)p->T_shell;
     P.attract = p->a != 0.0;
     P.gravity = (p->g[0] != 0.0 || p->g[1] != 0.0 || p->g[2] != 0.0);
@@ -318,12 +320,37 @@ bool buffer_path(const Layout &L) {
     return lo <= 0xFFFFFFFFull && hi <= 0xFFFFFFFFull;
 }
 
+// Dynamic LDS of a step launch: the u ring of the finite-difference
+// divergence (4 planes x 3 components over the tile and its halo), checked
+// against the device limit together with the kernel's static LDS.
+template <typename KernelFn>
+int step_lds_bytes(const lbm_handle *h, KernelFn kernel, int tx, int ty, size_t cs, size_t *dyn) {
+    *dyn = 0;
+    if (h->p.divu_mode != LBM_DIVU_FD) return LBM_OK;
+    *dyn = 4 * 3 * (size_t)(tx + 2) * (ty + 2) * cs;
+    hipFuncAttributes fa;
+    int dev = 0, limit = 0;
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(kernel)) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return LBM_EHIP;
+    return fa.sharedSizeBytes + *dyn <= (size_t)limit ? LBM_OK : LBM_EINVAL;
+}
+
 template <typename ST, int TX, int TY, bool WALLS>
 int launch_step_t(lbm_handle *h, const lbm::StepArgs<ST> &A, int nb) {
-    if (buffer_path(h->L))
-        hipLaunchKernelGGL((lbm::k_step<ST, TX, TY, WALLS, true>), dim3(nb), dim3(TX * TY), 0, h->stream, A);
-    else
-        hipLaunchKernelGGL((lbm::k_step<ST, TX, TY, WALLS, false>), dim3(nb), dim3(TX * TY), 0, h->stream, A);
+    const size_t cs = sizeof(typename ST::C);
+    size_t dyn = 0;
+    int rc;
+    if (buffer_path(h->L)) {
+        auto kernel = lbm::k_step<ST, TX, TY, WALLS, true>;
+        if ((rc = step_lds_bytes(h, kernel, TX, TY, cs, &dyn))) return rc;
+        hipLaunchKernelGGL(kernel, dim3(nb), dim3(TX * TY), dyn, h->stream, A);
+    } else {
+        auto kernel = lbm::k_step<ST, TX, TY, WALLS, false>;
+        if ((rc = step_lds_bytes(h, kernel, TX, TY, cs, &dyn))) return rc;
+        hipLaunchKernelGGL(kernel, dim3(nb), dim3(TX * TY), dyn, h->stream, A);
+    }
     return hip_status(hipGetLastError());
 }
 
@@ -363,6 +390,22 @@ int step_once(lbm_handle *h) {
     A.nty = (h->p.ny + h->tile_y - 1) / h->tile_y;
     A.cz = h->chunk_z;
     A.P = make_phys<C>(&h->p);
+    A.ustage = nullptr;
+    A.unn = h->L.nn;
+    if (A.P.divu_fd) {
+        // u(t) of Eq. (10) at every node for the finite-difference divergence:
+        // rho, T, psi and then u into the FP64 staging planes 0 and 1..3.
+        const lbm::Phys<double> P64 = make_phys<double>(&h->p);
+        const size_t nn = h->L.nn;
+        const int nbn = (int)((nn + 255) / 256);
+        double *st = h->stage();
+        hipLaunchKernelGGL(lbm::k_macro<ST>, dim3(nbn), dim3(256), 0, h->stream, (const T *)h->pop(c), h->L.stride,
+                           nn, P64, st);
+        hipLaunchKernelGGL(lbm::k_velocity<ST>, dim3(nbn), dim3(256), 0, h->stream, (const T *)h->pop(c),
+                           h->L.stride, h->p.nx, h->p.ny, h->p.nz, (int)(h->p.bc_z == LBM_BC_WALL_BOTTOM_OPEN_TOP), P64,
+                           (const double *)h->rho_ave(), st);
+        A.ustage = st + nn;
+    }
     const int nb = h->workgroups;
     int rc = h->p.bc_z == LBM_BC_WALL_BOTTOM_OPEN_TOP ? launch_step_tile<ST, true>(h, A, nb)
                                                       : launch_step_tile<ST, false>(h, A, nb);
@@ -662,7 +705,8 @@ int lbm_get_launch(const lbm_handle *h, int *tile_x, int *tile_y, int *chunk_z, 
 
 int lbm_launches_per_step(const lbm_handle *h) {
     if (!h) return 0;
-    return (h->p.g[0] != 0.0 || h->p.g[1] != 0.0 || h->p.g[2] != 0.0) ? 2 : 1;
+    return ((h->p.g[0] != 0.0 || h->p.g[1] != 0.0 || h->p.g[2] != 0.0) ? 2 : 1) +
+           (h->p.divu_mode == LBM_DIVU_FD ? 2 : 0);
 }
 
 void lbm_destroy(lbm_handle *h) { free(h); }
@@ -718,6 +762,7 @@ bool valid_batch(const lbm_params *cases, int n) {
         if (!valid_params(p) || p->storage != cases[0].storage || p->bc_z != LBM_BC_PERIODIC) return false;
         if (p->g[0] != 0.0 || p->g[1] != 0.0 || p->g[2] != 0.0) return false;
         if (p->thermal_lattice != LBM_THERMAL_D3Q7) return false;  // the batched kernel is built for D3Q7
+        if (p->divu_mode != LBM_DIVU_LOCAL) return false;          // and for the local divergence
     }
     return true;
 }

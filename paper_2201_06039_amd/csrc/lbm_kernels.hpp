@@ -83,6 +83,7 @@ struct Phys {
     int thermal;          // temperature lattice evolves
     int shell;            // outer layer of nodes held at T_shell (periodic grids only)
     int thermal_bgk;      // single relaxation time for the temperature lattice, Eq. (19)
+    int divu_fd;          // div u by isotropic finite differences of u at interior nodes
     C T_shell;
     int attract;          // a != 0
     int gravity;          // g != 0
@@ -564,10 +565,18 @@ struct StepArgs {
     double *__restrict__ partials;  // per-workgroup sum of rho (when gravity is on)
     unsigned *__restrict__ status;
     size_t stride;                  // elements between population planes
+    // u(t) of Eq. (10) at every node, component planes `unn` doubles apart
+    // (finite-difference divergence only; written by k_macro + k_velocity)
+    const double *__restrict__ ustage;
+    size_t unn;
     int nx, ny, nz;
     int ntx, nty, cz;               // tiles in x, y; planes per chunk
     Phys<typename ST::C> P;
 };
+
+// Dynamic LDS of the step kernel: the 4-plane ring of u (3 components) over
+// the tile and its halo, present only for the finite-difference divergence.
+extern __shared__ __attribute__((aligned(16))) unsigned char lbm_dyn_lds[];
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
 // b mod 8).  Give each XCD a contiguous range of logical tiles, so that
@@ -760,6 +769,17 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     };
     // rho, T, psi (and the rounded references) of a loaded plane, tile node
     // and halo node, into LDS slot `slot`.
+    // u of the tile and halo nodes of plane zp into ring slot `slot`
+    // (finite-difference divergence only).
+    C(*s_u)[3][NE] = reinterpret_cast<C(*)[3][NE]>(lbm_dyn_lds);
+    auto plane_velocity = [&](int slot, int zp) {
+        const size_t zoff = (size_t)zmap(zp) * plane;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            s_u[slot][c][li] = (C)A.ustage[c * A.unn + zoff + irow];
+            if (has_halo) s_u[slot][c][hli] = (C)A.ustage[c * A.unn + zoff + hrow];
+        }
+    };
     auto plane_moments = [&](int slot, const Node &kraw, const Node &hraw, C &krho, C &kT, C &kpsi) {
         const Pops k = decode(kraw);
         const C rho = node_rho(k), T = node_T(k);
@@ -936,7 +956,22 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
             for (int a = 0; a < QT; ++a) gs[a] = C(0);
         } else if (P.thermal) {
             // Eq. (48): local velocity divergence (pre-collision m_4).
-            const C divu = fmad(P.divu_b, S4, -fmad(P.divu_a, m[4] - meq[4], C(2) * Fu)) * (C(1.5) * inv_rhoK);
+            C divu = fmad(P.divu_b, S4, -fmad(P.divu_a, m[4] - meq[4], C(2) * Fu)) * (C(1.5) * inv_rhoK);
+            if (P.divu_fd && (!WALLS || (z > 0 && z < nz - 1))) {
+                // The practice Eq. (48) replaces: sum omega(|e|^2) e . u(x + e)
+                // over the 18 neighbours at interior nodes.
+#define NU(c, sl, dx, dy) s_u[sl][c][li + (dy) * EX + (dx)]
+                const C ax = (NU(0, s0, 1, 0) - NU(0, s0, -1, 0)) + (NU(1, s0, 0, 1) - NU(1, s0, 0, -1)) +
+                             (NU(2, sp, 0, 0) - NU(2, sm, 0, 0));
+                const C dxy = ((NU(0, s0, 1, 1) + NU(1, s0, 1, 1)) - (NU(0, s0, -1, -1) + NU(1, s0, -1, -1))) +
+                              ((NU(0, s0, 1, -1) - NU(1, s0, 1, -1)) - (NU(0, s0, -1, 1) - NU(1, s0, -1, 1)));
+                const C dxz = ((NU(0, sp, 1, 0) + NU(2, sp, 1, 0)) - (NU(0, sm, -1, 0) + NU(2, sm, -1, 0))) +
+                              ((NU(0, sm, 1, 0) - NU(2, sm, 1, 0)) - (NU(0, sp, -1, 0) - NU(2, sp, -1, 0)));
+                const C dyz = ((NU(1, sp, 0, 1) + NU(2, sp, 0, 1)) - (NU(1, sm, 0, -1) + NU(2, sm, 0, -1))) +
+                              ((NU(1, sm, 0, 1) - NU(2, sm, 0, 1)) - (NU(1, sp, 0, -1) - NU(2, sp, 0, -1)));
+#undef NU
+                divu = fmad(C(1.0 / 6.0), ax, C(1.0 / 12.0) * ((dxy + dxz) + dyz));
+            }
             // First moments sum e g (the reference part w T_r cancels): n1..n3
             // of Eq. (38) on D3Q7, the same sums over the 19 velocities on D3Q19.
             C n1, n2, n3, n5 = C(0), n6 = C(0);
@@ -1170,10 +1205,15 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         load_plane(z0 + 1, nxt, nxh);
         plane_moments(0, t0, th0, a0, a1, a2);
         plane_moments(1, cur, h0, c_rho, c_T, c_psi);
+        if (P.divu_fd) {
+            plane_velocity(0, z0 - 1);
+            plane_velocity(1, z0);
+        }
     }
     for (int z = z0; z < zend; ++z) {
         const int s = z - z0 + 1;
         plane_moments((s + 1) & 3, nxt, nxh, n_rho, n_T, n_psi);
+        if (P.divu_fd) plane_velocity((s + 1) & 3, z + 1);
         if (z + 2 <= zend) load_plane(z + 2, nq, nqh);
         __syncthreads();
         if (active) collide_stream(z, s, cur, c_rho, c_T, c_psi);

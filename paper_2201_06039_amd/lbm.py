@@ -35,7 +35,7 @@ class LbmParams(ctypes.Structure):
         ("patch_radius", ctypes.c_double), ("T_top", ctypes.c_double),
         ("thermal", ctypes.c_int), ("storage", ctypes.c_int),
         ("bc_T_shell", ctypes.c_int), ("T_shell", ctypes.c_double), ("thermal_bgk", ctypes.c_int),
-        ("thermal_lattice", ctypes.c_int),
+        ("thermal_lattice", ctypes.c_int), ("divu_mode", ctypes.c_int),
     ]
 
 
@@ -123,6 +123,7 @@ def make_params(params: dict, storage="f32") -> LbmParams:
     src.setdefault("T_shell", 0.0)
     src.setdefault("thermal_bgk", 0)
     src.setdefault("thermal_lattice", 0)
+    src.setdefault("divu_mode", 0)
     for n in names:
         if n not in src:
             raise KeyError(f"missing parameter {n!r}")

@@ -149,3 +149,14 @@ def test_d3q19_temperature_lattice_arena_and_validation(lib):
     a = dict(W.load("static_droplet_32")["params"])
     assert lbm.batch_arena_bytes([a, a], "f16") > 0
     assert lbm.batch_arena_bytes([a, dict(a, thermal_lattice=1, thermal_bgk=1)], "f16") == 0
+
+
+def test_divergence_mode_validation(lib):
+    """div u of Eq. (48) (LBM_DIVU_LOCAL) or by finite differences
+    (LBM_DIVU_FD); the finite-difference form is not built into batches."""
+    from paper_2201_06039_amd import lbm, workloads as W
+    p = dict(W.load("static_droplet_32")["params"])
+    assert lbm.arena_bytes(dict(p, divu_mode=1)) == lbm.arena_bytes(p) > 0
+    assert lbm.arena_bytes(dict(p, divu_mode=2)) == 0
+    assert lbm.arena_bytes(dict(p, divu_mode=-1)) == 0
+    assert lbm.batch_arena_bytes([p, dict(p, divu_mode=1)], "f16") == 0

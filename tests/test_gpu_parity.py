@@ -275,3 +275,59 @@ def test_d3q19_temperature_lattice_launch_shape_bitwise(storage):
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
             assert np.array_equal(a, b)
+
+
+# Finite-difference velocity divergence at interior nodes (LBM_DIVU_FD), the
+# practice Eq. (48) replaces; Eq. (48) stays at the wall layers.
+FD_CASES = [
+    ("evaporation_128", dict(nx=40, ny=40, nz=40, radius=9.0), 60, {}),
+    ("pool_boiling_32x32x48", {}, 50, {}),
+    ("evaporation_128", dict(nx=24, ny=20, nz=17, radius=5.0), 40, Q19T),
+]
+
+
+@pytest.mark.parametrize("case", FD_CASES, ids=["evaporation", "pool_boiling", "d3q19_ragged"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_fd_divergence_against_oracle(storage, case):
+    name, ov, steps, extra = case
+    w = workload(name, **ov, **extra, divu_mode=1)
+    _say(f"FD divergence {name} {ov} {extra} {storage} steps={steps}")
+    ref = run_oracle(w, steps)
+    e = errors(run_gpu(w, steps, storage), ref)
+    _say(f"  errors {e}")
+    if storage == "f64":
+        _check(e, FP64_TOL)
+    elif storage == "f32":
+        tu = fp32_u_tol(steps, ref)
+        _check(e, FP32_TOL, keys=("rho", "T"))
+        assert e["u_l2"] <= tu and e["u"] <= 2 * tu, (tu, e)
+    else:
+        tol = DEV_TOL["f16"]
+        assert e["rho"] <= tol and e["T"] <= tol and e["u_l2"] <= 20 * tol, e
+
+
+def test_fd_divergence_launch_shapes():
+    """Every launch shape whose LDS fits gives the same bits; one that does not
+    fit is refused with EINVAL, not run."""
+    from paper_2201_06039_amd import lbm
+    w = workload("evaporation_128", nx=40, ny=36, nz=20, radius=7.0, divu_mode=1)
+    outs = []
+    for launch in [(64, 4, 4), (32, 8, 7), (64, 4, 20), (32, 8, 1)]:
+        _say(f"FD divergence f32 launch {launch}")
+        outs.append(run_gpu(w, 25, "f32", launch=launch))
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+    for launch in [(128, 4, 8), (64, 8, 8)]:
+        _say(f"FD divergence f16 launch {launch}")
+        try:
+            o = run_gpu(w, 25, "f16", launch=launch)
+        except lbm.LbmError as exc:
+            assert exc.status == lbm.EINVAL, exc
+            continue
+        ref = run_gpu(w, 25, "f16", launch=(64, 4, 8))
+        for a, b in zip(ref, o):
+            assert np.array_equal(a, b)
+    lat = lbm.Lattice(w["params"], storage="f32", device="cuda:0")
+    assert lat.launches_per_step() == 3
+    lat.close()
