@@ -75,6 +75,8 @@ bool valid_params(const lbm_params *p) {
     // temperature lattice takes the BGK collision.
     if (p->thermal_lattice != LBM_THERMAL_D3Q7 && p->thermal_lattice != LBM_THERMAL_D3Q19) return false;
     if (p->divu_mode != LBM_DIVU_LOCAL && p->divu_mode != LBM_DIVU_FD) return false;
+    if (p->divu_mode == LBM_DIVU_FD && (p->storage == LBM_STORE_BF16 || p->storage == LBM_STORE_F32_DEV))
+        return false;
     if (p->thermal_lattice == LBM_THERMAL_D3Q19 &&
         (!p->thermal_bgk || p->storage == LBM_STORE_BF16 || p->storage == LBM_STORE_F32_DEV))
         return false;
@@ -193,7 +195,6 @@ lbm::Phys<C> make_phys(const lbm_params *p) {
     P.thermal = p->thermal;
     P.shell = p->bc_T_shell;
     P.thermal_bgk = p->thermal_bgk;
-    P.divu_fd = p->divu_mode == LBM_DIVU_FD;
     P.T_shell = (C)p->T_shell;
     P.attract = p->a != 0.0;
     P.gravity = (p->g[0] != 0.0 || p->g[1] != 0.0 || p->g[2] != 0.0);
@@ -294,6 +295,11 @@ void set_default_launch(lbm_handle *h) {
         h->tile_x = (half && nx >= 96) ? 128 : 64;
         h->tile_y = 4;
     }
+    if (h->p.divu_mode == LBM_DIVU_FD && h->tile_x * h->tile_y != 256) {
+        // the finite-difference divergence is built for 256-thread tiles
+        h->tile_x = nx > 32 ? 64 : 32;
+        h->tile_y = nx > 32 ? 4 : 8;
+    }
     if (h->p.storage == LBM_STORE_F64 && h->tile_x * h->tile_y != 256) {
         h->tile_x = nx > 32 ? 64 : 32;
         h->tile_y = nx > 32 ? 4 : 8;
@@ -320,38 +326,37 @@ bool buffer_path(const Layout &L) {
     return lo <= 0xFFFFFFFFull && hi <= 0xFFFFFFFFull;
 }
 
-// Dynamic LDS of a step launch: the u ring of the finite-difference
-// divergence (4 planes x 3 components over the tile and its halo), checked
-// against the device limit together with the kernel's static LDS.
-template <typename KernelFn>
-int step_lds_bytes(const lbm_handle *h, KernelFn kernel, int tx, int ty, size_t cs, size_t *dyn) {
-    *dyn = 0;
-    if (h->p.divu_mode != LBM_DIVU_FD) return LBM_OK;
-    *dyn = 4 * 3 * (size_t)(tx + 2) * (ty + 2) * cs;
-    hipFuncAttributes fa;
-    int dev = 0, limit = 0;
-    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(kernel)) != hipSuccess ||
-        hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-        return LBM_EHIP;
-    return fa.sharedSizeBytes + *dyn <= (size_t)limit ? LBM_OK : LBM_EINVAL;
-}
-
 template <typename ST, int TX, int TY, bool WALLS>
 int launch_step_t(lbm_handle *h, const lbm::StepArgs<ST> &A, int nb) {
-    const size_t cs = sizeof(typename ST::C);
-    size_t dyn = 0;
-    int rc;
-    if (buffer_path(h->L)) {
-        auto kernel = lbm::k_step<ST, TX, TY, WALLS, true>;
-        if ((rc = step_lds_bytes(h, kernel, TX, TY, cs, &dyn))) return rc;
-        hipLaunchKernelGGL(kernel, dim3(nb), dim3(TX * TY), dyn, h->stream, A);
-    } else {
-        auto kernel = lbm::k_step<ST, TX, TY, WALLS, false>;
-        if ((rc = step_lds_bytes(h, kernel, TX, TY, cs, &dyn))) return rc;
-        hipLaunchKernelGGL(kernel, dim3(nb), dim3(TX * TY), dyn, h->stream, A);
-    }
+    if (buffer_path(h->L))
+        hipLaunchKernelGGL((lbm::k_step<ST, TX, TY, WALLS, true, false>), dim3(nb), dim3(TX * TY), 0, h->stream, A);
+    else
+        hipLaunchKernelGGL((lbm::k_step<ST, TX, TY, WALLS, false, false>), dim3(nb), dim3(TX * TY), 0, h->stream, A);
     return hip_status(hipGetLastError());
+}
+
+// The finite-difference divergence is built for the FP32, FP64 and FP16
+// formats, 256-thread tiles and the buffer-resource path (checked when the
+// parameters and the launch shape are set).
+template <typename ST>
+constexpr bool fd_built() {
+    return !std::is_same<typename ST::T, __bf16>::value && !(ST::kDev && sizeof(typename ST::T) == 4);
+}
+
+template <typename ST, bool WALLS>
+int launch_step_fd(lbm_handle *h, const lbm::StepArgs<ST> &A, int nb) {
+    if constexpr (fd_built<ST>()) {
+        if (!buffer_path(h->L)) return LBM_EINVAL;
+        if (h->tile_x == 64 && h->tile_y == 4)
+            hipLaunchKernelGGL((lbm::k_step<ST, 64, 4, WALLS, true, true>), dim3(nb), dim3(256), 0, h->stream, A);
+        else if (h->tile_x == 32 && h->tile_y == 8)
+            hipLaunchKernelGGL((lbm::k_step<ST, 32, 8, WALLS, true, true>), dim3(nb), dim3(256), 0, h->stream, A);
+        else
+            return LBM_EINVAL;
+        return hip_status(hipGetLastError());
+    } else {
+        return LBM_EINVAL;
+    }
 }
 
 // FP32-arithmetic formats instantiate every tile shape; the FP64 build (used
@@ -359,6 +364,7 @@ int launch_step_t(lbm_handle *h, const lbm::StepArgs<ST> &A, int nb) {
 // which fit its registers without spilling.
 template <typename ST, bool WALLS>
 int launch_step_tile(lbm_handle *h, const lbm::StepArgs<ST> &A, int nb) {
+    if (h->p.divu_mode == LBM_DIVU_FD) return launch_step_fd<ST, WALLS>(h, A, nb);
     const int tx = h->tile_x, ty = h->tile_y;
     if (tx == 64 && ty == 4) return launch_step_t<ST, 64, 4, WALLS>(h, A, nb);
     if (tx == 32 && ty == 8) return launch_step_t<ST, 32, 8, WALLS>(h, A, nb);
@@ -392,7 +398,7 @@ int step_once(lbm_handle *h) {
     A.P = make_phys<C>(&h->p);
     A.ustage = nullptr;
     A.unn = h->L.nn;
-    if (A.P.divu_fd) {
+    if (h->p.divu_mode == LBM_DIVU_FD) {
         // u(t) of Eq. (10) at every node for the finite-difference divergence:
         // rho, T, psi and then u into the FP64 staging planes 0 and 1..3.
         const lbm::Phys<double> P64 = make_phys<double>(&h->p);
@@ -682,7 +688,7 @@ int lbm_set_launch(lbm_handle *h, int tile_x, int tile_y, int chunk_z) {
     if (!h || chunk_z < 1 || chunk_z > kMaxChunk) return LBM_EINVAL;
     bool ok = false;
     for (const TileShape &t : kTiles) ok = ok || (t.tx == tile_x && t.ty == tile_y);
-    if (h->p.storage == LBM_STORE_F64) ok = ok && tile_x * tile_y == 256;
+    if (h->p.storage == LBM_STORE_F64 || h->p.divu_mode == LBM_DIVU_FD) ok = ok && tile_x * tile_y == 256;
     if (!ok) return LBM_EINVAL;
     const int cz = chunk_z > h->p.nz ? h->p.nz : chunk_z;
     const int nb = workgroups_for(h, tile_x, tile_y, cz);

@@ -83,7 +83,6 @@ struct Phys {
     int thermal;          // temperature lattice evolves
     int shell;            // outer layer of nodes held at T_shell (periodic grids only)
     int thermal_bgk;      // single relaxation time for the temperature lattice, Eq. (19)
-    int divu_fd;          // div u by isotropic finite differences of u at interior nodes
     C T_shell;
     int attract;          // a != 0
     int gravity;          // g != 0
@@ -566,7 +565,8 @@ struct StepArgs {
     unsigned *__restrict__ status;
     size_t stride;                  // elements between population planes
     // u(t) of Eq. (10) at every node, component planes `unn` doubles apart
-    // (finite-difference divergence only; written by k_macro + k_velocity)
+    // (finite-difference divergence only; written by k_macro + k_velocity
+    // before the step)
     const double *__restrict__ ustage;
     size_t unn;
     int nx, ny, nz;
@@ -574,9 +574,6 @@ struct StepArgs {
     Phys<typename ST::C> P;
 };
 
-// Dynamic LDS of the step kernel: the 4-plane ring of u (3 components) over
-// the tile and its halo, present only for the finite-difference divergence.
-extern __shared__ __attribute__((aligned(16))) unsigned char lbm_dyn_lds[];
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
 // b mod 8).  Give each XCD a contiguous range of logical tiles, so that
@@ -608,7 +605,9 @@ struct NodeWords {
 // One workgroup's share of a time step: the x-y tile and z chunk with index
 // `logical` (x fastest, then y, then the chunk), for the lattice described by
 // A.  `slot` is the workgroup's entry in A.partials (gravity runs only).
-template <typename ST, int TX, int TY, bool WALLS, bool BUF>
+// DFD: the velocity divergence by finite differences of A.ustage at interior
+// nodes instead of Eq. (48).
+template <typename ST, int TX, int TY, bool WALLS, bool BUF, bool DFD = false>
 __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, int slot) {
     using E = typename ST::T;  // stored element
     using C = typename ST::C;
@@ -771,7 +770,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     // and halo node, into LDS slot `slot`.
     // u of the tile and halo nodes of plane zp into ring slot `slot`
     // (finite-difference divergence only).
-    C(*s_u)[3][NE] = reinterpret_cast<C(*)[3][NE]>(lbm_dyn_lds);
+    __shared__ C s_u[DFD ? 4 : 1][3][DFD ? NE : 1];
     auto plane_velocity = [&](int slot, int zp) {
         const size_t zoff = (size_t)zmap(zp) * plane;
 #pragma unroll
@@ -957,7 +956,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         } else if (P.thermal) {
             // Eq. (48): local velocity divergence (pre-collision m_4).
             C divu = fmad(P.divu_b, S4, -fmad(P.divu_a, m[4] - meq[4], C(2) * Fu)) * (C(1.5) * inv_rhoK);
-            if (P.divu_fd && (!WALLS || (z > 0 && z < nz - 1))) {
+            if (DFD && (!WALLS || (z > 0 && z < nz - 1))) {
                 // The practice Eq. (48) replaces: sum omega(|e|^2) e . u(x + e)
                 // over the 18 neighbours at interior nodes.
 #define NU(c, sl, dx, dy) s_u[sl][c][li + (dy) * EX + (dx)]
@@ -1205,7 +1204,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         load_plane(z0 + 1, nxt, nxh);
         plane_moments(0, t0, th0, a0, a1, a2);
         plane_moments(1, cur, h0, c_rho, c_T, c_psi);
-        if (P.divu_fd) {
+        if constexpr (DFD) {
             plane_velocity(0, z0 - 1);
             plane_velocity(1, z0);
         }
@@ -1213,7 +1212,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     for (int z = z0; z < zend; ++z) {
         const int s = z - z0 + 1;
         plane_moments((s + 1) & 3, nxt, nxh, n_rho, n_T, n_psi);
-        if (P.divu_fd) plane_velocity((s + 1) & 3, z + 1);
+        if constexpr (DFD) plane_velocity((s + 1) & 3, z + 1);
         if (z + 2 <= zend) load_plane(z + 2, nq, nqh);
         __syncthreads();
         if (active) collide_stream(z, s, cur, c_rho, c_T, c_psi);
@@ -1239,9 +1238,9 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
 }
 
 // One launch per time step: workgroup b takes tile/chunk xcd_logical_block(b).
-template <typename ST, int TX, int TY, bool WALLS, bool BUF>
+template <typename ST, int TX, int TY, bool WALLS, bool BUF, bool DFD>
 __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
-    step_tile<ST, TX, TY, WALLS, BUF>(A, xcd_logical_block(blockIdx.x, gridDim.x), blockIdx.x);
+    step_tile<ST, TX, TY, WALLS, BUF, DFD>(A, xcd_logical_block(blockIdx.x, gridDim.x), blockIdx.x);
 }
 
 // Work list of a batch of independent lattices advanced by one launch.

@@ -160,3 +160,7 @@ def test_divergence_mode_validation(lib):
     assert lbm.arena_bytes(dict(p, divu_mode=2)) == 0
     assert lbm.arena_bytes(dict(p, divu_mode=-1)) == 0
     assert lbm.batch_arena_bytes([p, dict(p, divu_mode=1)], "f16") == 0
+    for fmt in ("f32", "f64", "f16"):
+        assert lbm.arena_bytes(dict(p, divu_mode=1), fmt) > 0, fmt
+    for fmt in ("bf16", "f32dev"):
+        assert lbm.arena_bytes(dict(p, divu_mode=1), fmt) == 0, fmt
