@@ -1,5 +1,5 @@
-"""Storage formats against the FP64 oracle on the quantities the method is
-judged by: coexistence densities of a flat slab, the Laplace pressure jump of
+"""Storage formats against the FP64 oracle on the quantities the paper
+validates the method with: coexistence densities of a flat slab, the Laplace pressure jump of
 a static droplet, and the D^2 slope of an evaporating droplet (Sec. IV A).
 
 Reference values come from tests/golden/precision_refs.json, written by the
