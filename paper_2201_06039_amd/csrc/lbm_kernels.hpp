@@ -1188,13 +1188,16 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     };
 
     // Software pipeline over the planes of the chunk.  At iteration z the
-    // states of plane z (collision) and z+1 (moments) are in registers, and
-    // the loads of plane z+2 are issued right after the moments of z+1 so that
-    // their latency overlaps the barrier and the collision of plane z.
-    // (Issuing them earlier would put more memory operations between a load
-    // and its use than the vmcnt counter can express, which forces a full
-    // drain.)
-    Node cur, nxt, nxh, nq, nqh;  // plane z; plane z+1 (tile, halo); plane z+2
+    // states of plane z (collision) and z+1 (moments) are in registers.  The
+    // loads of the tile node of plane z+2 are issued right after the moments
+    // of z+1, so that their latency overlaps the barrier and the collision of
+    // plane z; the loads of its halo node follow the collision, so that the
+    // halo words are not held across it (fewer live registers: measured 4%
+    // faster with FP16 storage, 9-12% with the D3Q19 temperature lattice, the
+    // same with FP32).  Issuing loads earlier would put more memory
+    // operations between a load and its use than the vmcnt counter can
+    // express, which forces a full drain.
+    Node cur, nxt, nxh, nq;  // plane z; plane z+1 (tile, halo); tile node of plane z+2
     C c_rho, c_T, c_psi, n_rho, n_T, n_psi;
     {
         Node t0, th0, h0;
@@ -1213,12 +1216,13 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         const int s = z - z0 + 1;
         plane_moments((s + 1) & 3, nxt, nxh, n_rho, n_T, n_psi);
         if constexpr (DFD) plane_velocity((s + 1) & 3, z + 1);
-        if (z + 2 <= zend) load_plane(z + 2, nq, nqh);
+        const unsigned zoff2 = (unsigned)zmap(z + 2) * plane;
+        if (z + 2 <= zend) load_node(irow, zoff2, nq);
         __syncthreads();
         if (active) collide_stream(z, s, cur, c_rho, c_T, c_psi);
         cur = nxt;
         nxt = nq;
-        nxh = nqh;
+        if (z + 2 <= zend && has_halo) load_node(hrow, zoff2, nxh);
         c_rho = n_rho;
         c_T = n_T;
         c_psi = n_psi;
