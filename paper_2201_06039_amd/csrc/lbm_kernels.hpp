@@ -1191,13 +1191,15 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     // states of plane z (collision) and z+1 (moments) are in registers.  The
     // loads of the tile node of plane z+2 are issued right after the moments
     // of z+1, so that their latency overlaps the barrier and the collision of
-    // plane z; the loads of its halo node follow the collision, so that the
-    // halo words are not held across it (fewer live registers: measured 4%
-    // faster with FP16 storage, 9-12% with the D3Q19 temperature lattice, the
-    // same with FP32).  Issuing loads earlier would put more memory
+    // plane z.  The loads of its halo node go with them for 4-byte D3Q7
+    // storage; for 16-bit storage and the D3Q19 temperature lattice they
+    // follow the collision, so that the halo words are not held across it
+    // (measured: FP16 4% faster at 128^3 and 7% at 256^3, D3Q19 9-12%; plain
+    // FP32 4% slower at 256^3).  Issuing loads earlier would put more memory
     // operations between a load and its use than the vmcnt counter can
     // express, which forces a full drain.
-    Node cur, nxt, nxh, nq;  // plane z; plane z+1 (tile, halo); tile node of plane z+2
+    constexpr bool LATE_HALO = sizeof(E) == 2 || QT == 19;
+    Node cur, nxt, nxh, nq, nqh;  // plane z; plane z+1 (tile, halo); plane z+2 (tile, halo)
     C c_rho, c_T, c_psi, n_rho, n_T, n_psi;
     {
         Node t0, th0, h0;
@@ -1217,12 +1219,19 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         plane_moments((s + 1) & 3, nxt, nxh, n_rho, n_T, n_psi);
         if constexpr (DFD) plane_velocity((s + 1) & 3, z + 1);
         const unsigned zoff2 = (unsigned)zmap(z + 2) * plane;
-        if (z + 2 <= zend) load_node(irow, zoff2, nq);
+        if (z + 2 <= zend) {
+            load_node(irow, zoff2, nq);
+            if (!LATE_HALO && has_halo) load_node(hrow, zoff2, nqh);
+        }
         __syncthreads();
         if (active) collide_stream(z, s, cur, c_rho, c_T, c_psi);
         cur = nxt;
         nxt = nq;
-        if (z + 2 <= zend && has_halo) load_node(hrow, zoff2, nxh);
+        if constexpr (LATE_HALO) {
+            if (z + 2 <= zend && has_halo) load_node(hrow, zoff2, nxh);
+        } else {
+            nxh = nqh;
+        }
         c_rho = n_rho;
         c_T = n_T;
         c_psi = n_psi;
