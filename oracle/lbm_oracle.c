@@ -687,6 +687,7 @@ int orc_init_fields(orc_sim *s, const double *rho, const double *ux, const doubl
         if (!(rho[i] > 0.0) || !(T[i] > 0.0) || !(psi_squared(&s->p, s->Tc, rho[i], T[i]) >= 0.0))
             return ORC_EINVAL;
     }
+#pragma omp parallel for schedule(static)
     for (long i = 0; i < nn; ++i) {
         const double u[3] = {ux[i], uy[i], uz[i]};
         double meq[Q19];
