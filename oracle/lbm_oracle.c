@@ -657,16 +657,17 @@ int orc_create(const orc_params *p, orc_sim **out) {
     s->f = calloc(Q19 * nn, sizeof(double));
     s->fs = calloc(Q19 * nn, sizeof(double));
     s->fn = calloc(Q19 * nn, sizeof(double));
-    s->g = calloc(Q19 * nn, sizeof(double));
-    s->gp = calloc(Q19 * nn, sizeof(double));
-    s->gn = calloc(Q19 * nn, sizeof(double));
+    const long qt = p->thermal_lattice ? Q19 : Q7;
+    s->g = calloc(qt * nn, sizeof(double));
+    s->gp = calloc(qt * nn, sizeof(double));
+    s->gn = calloc(qt * nn, sizeof(double));
     s->phi_prev = calloc(nn, sizeof(double));
     s->rho = calloc(nn, sizeof(double));
     s->T = calloc(nn, sizeof(double));
     s->psi = calloc(nn, sizeof(double));
     s->Fm = calloc(3 * nn, sizeof(double));
     s->grho = calloc(3 * nn, sizeof(double));
-    s->uall = calloc(3 * nn, sizeof(double));
+    s->uall = calloc(p->divu_mode ? 3 * nn : 1, sizeof(double));
     if (!s->f || !s->fs || !s->fn || !s->g || !s->gp || !s->gn || !s->phi_prev || !s->rho || !s->T ||
         !s->psi || !s->Fm || !s->grho || !s->uall) {
         orc_destroy(s);

@@ -331,3 +331,4 @@ def test_fd_divergence_launch_shapes():
     lat = lbm.Lattice(w["params"], storage="f32", device="cuda:0")
     assert lat.launches_per_step() == 3
     lat.close()
+
