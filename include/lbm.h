@@ -70,12 +70,12 @@ extern "C" {
                          /* differences sum omega(|e|^2) e . u(x + e) of u(t) of */
                          /* Eq. (10) at interior nodes, Eq. (48) at the layers   */
                          /* next to a wall or the open top.  Each step first     */
-                         /* computes u at every node (two more launches into the */
-                         /* FP64 staging planes).  Built for storage F32, F64    */
-                         /* and F16, tiles 64x4 and 32x8, and copies whose two   */
-                         /* halves (planes below and above the split) each stay  */
-                         /* under 4 GiB (lbm_step returns EINVAL otherwise); not */
-                         /* in batches                                           */
+                         /* writes u at every node into the staging region (a   */
+                         /* velocity pass: one more launch of the step's shape). */
+                         /* Built for storage F32, F64 and F16, and copies whose */
+                         /* two halves (planes below and above the split) each   */
+                         /* stay under 4 GiB (lbm_step returns EINVAL            */
+                         /* otherwise); not in batches                           */
 
 /* Storage format of the populations.
  *   F32, F64: the populations f, g themselves; arithmetic in the same type.
@@ -189,13 +189,12 @@ int lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes);
  * nodes per workgroup marching over chunk_z planes.  Supported tiles:
  * 64x4, 32x8, 64x8, 32x16, 128x4 (F64 storage: 64x4 and 32x8 only);
  * chunk_z >= 1 (values above nz are clamped to nz).  EINVAL otherwise.
- * With LBM_DIVU_FD only the 64x4 and 32x8 tiles.
  * The result of a step does not depend on the launch shape. */
 int lbm_set_launch(lbm_handle *h, int tile_x, int tile_y, int chunk_z);
 int lbm_get_launch(const lbm_handle *h, int *tile_x, int *tile_y, int *chunk_z, int *workgroups);
 
 /* Number of kernel launches lbm_step() enqueues per time step: 1, plus 1
- * when gravity needs the rho_ave reduction, plus 2 with LBM_DIVU_FD. */
+ * when gravity needs the rho_ave reduction, plus 1 with LBM_DIVU_FD. */
 int lbm_launches_per_step(const lbm_handle *h);
 
 /* Release host resources; the arena stays with the caller.  NULL-safe. */

@@ -295,11 +295,6 @@ void set_default_launch(lbm_handle *h) {
         h->tile_x = (half && nx >= 96) ? 128 : 64;
         h->tile_y = 4;
     }
-    if (h->p.divu_mode == LBM_DIVU_FD && h->tile_x * h->tile_y != 256) {
-        // the finite-difference divergence is built for 256-thread tiles
-        h->tile_x = nx > 32 ? 64 : 32;
-        h->tile_y = nx > 32 ? 4 : 8;
-    }
     if (h->p.storage == LBM_STORE_F64 && h->tile_x * h->tile_y != 256) {
         h->tile_x = nx > 32 ? 64 : 32;
         h->tile_y = nx > 32 ? 4 : 8;
@@ -343,17 +338,29 @@ constexpr bool fd_built() {
     return !std::is_same<typename ST::T, __bf16>::value && !(ST::kDev && sizeof(typename ST::T) == 4);
 }
 
+// A step with the finite-difference divergence is two launches of the same
+// shape: the velocity pass (u(t) of every node into the staging region) and
+// the step that reads it.
+template <typename ST, int TX, int TY, bool WALLS>
+int launch_fd_t(lbm_handle *h, const lbm::StepArgs<ST> &A, int nb) {
+    hipLaunchKernelGGL((lbm::k_velocity_pass<ST, TX, TY, WALLS, true>), dim3(nb), dim3(TX * TY), 0, h->stream, A);
+    hipLaunchKernelGGL((lbm::k_step<ST, TX, TY, WALLS, true, true>), dim3(nb), dim3(TX * TY), 0, h->stream, A);
+    return hip_status(hipGetLastError());
+}
+
 template <typename ST, bool WALLS>
 int launch_step_fd(lbm_handle *h, const lbm::StepArgs<ST> &A, int nb) {
     if constexpr (fd_built<ST>()) {
         if (!buffer_path(h->L)) return LBM_EINVAL;
-        if (h->tile_x == 64 && h->tile_y == 4)
-            hipLaunchKernelGGL((lbm::k_step<ST, 64, 4, WALLS, true, true>), dim3(nb), dim3(256), 0, h->stream, A);
-        else if (h->tile_x == 32 && h->tile_y == 8)
-            hipLaunchKernelGGL((lbm::k_step<ST, 32, 8, WALLS, true, true>), dim3(nb), dim3(256), 0, h->stream, A);
-        else
-            return LBM_EINVAL;
-        return hip_status(hipGetLastError());
+        const int tx = h->tile_x, ty = h->tile_y;
+        if (tx == 64 && ty == 4) return launch_fd_t<ST, 64, 4, WALLS>(h, A, nb);
+        if (tx == 32 && ty == 8) return launch_fd_t<ST, 32, 8, WALLS>(h, A, nb);
+        if constexpr (sizeof(typename ST::C) == 4) {
+            if (tx == 64 && ty == 8) return launch_fd_t<ST, 64, 8, WALLS>(h, A, nb);
+            if (tx == 32 && ty == 16) return launch_fd_t<ST, 32, 16, WALLS>(h, A, nb);
+            if (tx == 128 && ty == 4) return launch_fd_t<ST, 128, 4, WALLS>(h, A, nb);
+        }
+        return LBM_EINVAL;
     } else {
         return LBM_EINVAL;
     }
@@ -396,22 +403,11 @@ int step_once(lbm_handle *h) {
     A.nty = (h->p.ny + h->tile_y - 1) / h->tile_y;
     A.cz = h->chunk_z;
     A.P = make_phys<C>(&h->p);
-    A.ustage = nullptr;
+    // u(t) planes of the finite-difference divergence: the staging region
+    // (six FP64 planes) holds the three planes in the compute type.
+    A.uout = (C *)h->stage();
+    A.ustage = A.uout;
     A.unn = h->L.nn;
-    if (h->p.divu_mode == LBM_DIVU_FD) {
-        // u(t) of Eq. (10) at every node for the finite-difference divergence:
-        // rho, T, psi and then u into the FP64 staging planes 0 and 1..3.
-        const lbm::Phys<double> P64 = make_phys<double>(&h->p);
-        const size_t nn = h->L.nn;
-        const int nbn = (int)((nn + 255) / 256);
-        double *st = h->stage();
-        hipLaunchKernelGGL(lbm::k_macro<ST>, dim3(nbn), dim3(256), 0, h->stream, (const T *)h->pop(c), h->L.stride,
-                           nn, P64, st);
-        hipLaunchKernelGGL(lbm::k_velocity<ST>, dim3(nbn), dim3(256), 0, h->stream, (const T *)h->pop(c),
-                           h->L.stride, h->p.nx, h->p.ny, h->p.nz, (int)(h->p.bc_z == LBM_BC_WALL_BOTTOM_OPEN_TOP), P64,
-                           (const double *)h->rho_ave(), st);
-        A.ustage = st + nn;
-    }
     const int nb = h->workgroups;
     int rc = h->p.bc_z == LBM_BC_WALL_BOTTOM_OPEN_TOP ? launch_step_tile<ST, true>(h, A, nb)
                                                       : launch_step_tile<ST, false>(h, A, nb);
@@ -688,7 +684,7 @@ int lbm_set_launch(lbm_handle *h, int tile_x, int tile_y, int chunk_z) {
     if (!h || chunk_z < 1 || chunk_z > kMaxChunk) return LBM_EINVAL;
     bool ok = false;
     for (const TileShape &t : kTiles) ok = ok || (t.tx == tile_x && t.ty == tile_y);
-    if (h->p.storage == LBM_STORE_F64 || h->p.divu_mode == LBM_DIVU_FD) ok = ok && tile_x * tile_y == 256;
+    if (h->p.storage == LBM_STORE_F64) ok = ok && tile_x * tile_y == 256;
     if (!ok) return LBM_EINVAL;
     const int cz = chunk_z > h->p.nz ? h->p.nz : chunk_z;
     const int nb = workgroups_for(h, tile_x, tile_y, cz);
@@ -712,7 +708,7 @@ int lbm_get_launch(const lbm_handle *h, int *tile_x, int *tile_y, int *chunk_z, 
 int lbm_launches_per_step(const lbm_handle *h) {
     if (!h) return 0;
     return ((h->p.g[0] != 0.0 || h->p.g[1] != 0.0 || h->p.g[2] != 0.0) ? 2 : 1) +
-           (h->p.divu_mode == LBM_DIVU_FD ? 2 : 0);
+           (h->p.divu_mode == LBM_DIVU_FD ? 1 : 0);
 }
 
 void lbm_destroy(lbm_handle *h) { free(h); }
@@ -866,6 +862,9 @@ int build_batch_tables(lbm_batch *b) {
         A.partials = h->partials();
         A.status = h->status();
         A.stride = h->L.stride;
+        A.ustage = nullptr;  // batches run the local divergence of Eq. (48)
+        A.uout = nullptr;
+        A.unn = 0;
         A.nx = h->p.nx;
         A.ny = h->p.ny;
         A.nz = h->p.nz;

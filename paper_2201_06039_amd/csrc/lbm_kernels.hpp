@@ -564,10 +564,11 @@ struct StepArgs {
     double *__restrict__ partials;  // per-workgroup sum of rho (when gravity is on)
     unsigned *__restrict__ status;
     size_t stride;                  // elements between population planes
-    // u(t) of Eq. (10) at every node, component planes `unn` doubles apart
-    // (finite-difference divergence only; written by k_macro + k_velocity
-    // before the step)
-    const double *__restrict__ ustage;
+    // u(t) of Eq. (10) at every node, component planes `unn` values apart
+    // (finite-difference divergence only): written by the velocity pass
+    // (uout), read by the step (ustage)
+    const typename ST::C *__restrict__ ustage;
+    typename ST::C *__restrict__ uout;
     size_t unn;
     int nx, ny, nz;
     int ntx, nty, cz;               // tiles in x, y; planes per chunk
@@ -606,8 +607,10 @@ struct NodeWords {
 // `logical` (x fastest, then y, then the chunk), for the lattice described by
 // A.  `slot` is the workgroup's entry in A.partials (gravity runs only).
 // DFD: the velocity divergence by finite differences of A.ustage at interior
-// nodes instead of Eq. (48).
-template <typename ST, int TX, int TY, bool WALLS, bool BUF, bool DFD = false>
+// nodes instead of Eq. (48).  VEL: the velocity pass that precedes such a
+// step -- the same march over the planes (rho, T, psi and the LDS ring), but
+// each tile node only writes u(t) of Eq. (10) to A.uout.
+template <typename ST, int TX, int TY, bool WALLS, bool BUF, bool DFD = false, bool VEL = false>
 __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, int slot) {
     using E = typename ST::T;  // stored element
     using C = typename ST::C;
@@ -775,8 +778,8 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         const size_t zoff = (size_t)zmap(zp) * plane;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            s_u[slot][c][li] = (C)A.ustage[c * A.unn + zoff + irow];
-            if (has_halo) s_u[slot][c][hli] = (C)A.ustage[c * A.unn + zoff + hrow];
+            s_u[slot][c][li] = A.ustage[c * A.unn + zoff + irow];
+            if (has_halo) s_u[slot][c][hli] = A.ustage[c * A.unn + zoff + hrow];
         }
     };
     auto plane_moments = [&](int slot, const Node &kraw, const Node &hraw, C &krho, C &kT, C &kpsi) {
@@ -1187,6 +1190,37 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         if (P.gravity) rho_sum += (double)rho;
     };
 
+    // Velocity pass: u(t) of the tile node at plane z (slot s), computed as in
+    // collide_stream (Eq. (7), (10)).
+    auto velocity_out = [&](int z, int s, const Node &ndraw, C rho, C psi) {
+        const Pops nd = decode(ndraw);
+        const int sm = (s + 3) & 3, s0 = s & 3, sp = (s + 1) & 3;
+#define NB(dx, dy, sl) s_psi[sl][li + (dy) * EX + (dx)]
+        const C xy = NB(1, 1, s0) - NB(-1, -1, s0), xmy = NB(1, -1, s0) - NB(-1, 1, s0);
+        const C xz = NB(1, 0, sp) - NB(-1, 0, sm), xmz = NB(1, 0, sm) - NB(-1, 0, sp);
+        const C yz = NB(0, 1, sp) - NB(0, -1, sm), ymz = NB(0, 1, sm) - NB(0, -1, sp);
+        const C Spx = fmad(C(1.0 / 6.0), NB(1, 0, s0) - NB(-1, 0, s0), C(1.0 / 12.0) * ((xy + xmy) + (xz + xmz)));
+        const C Spy = fmad(C(1.0 / 6.0), NB(0, 1, s0) - NB(0, -1, s0), C(1.0 / 12.0) * ((xy - xmy) + (yz + ymz)));
+        const C Spz = fmad(C(1.0 / 6.0), NB(0, 0, sp) - NB(0, 0, sm), C(1.0 / 12.0) * ((xz - xmz) + (yz - ymz)));
+#undef NB
+        const C inv_rho = Num<C>::rcp(rho);
+        const C gpsi = P.negG * psi;
+        C Fx = gpsi * Spx, Fy = gpsi * Spy, Fz = gpsi * Spz;
+        if (P.gravity) {
+            const C drho = rho - rho_ave;
+            Fx = fmad(drho, P.gx, Fx);
+            Fy = fmad(drho, P.gy, Fy);
+            Fz = fmad(drho, P.gz, Fz);
+        }
+        const C inv_rhoK = IK * inv_rho;
+        C m[19];
+        moments19<C, true>(nd.e, m, K * (rho - nd.br));
+        const unsigned own = (unsigned)z * plane + irow;
+        A.uout[own] = fmad(C(0.5), K * Fx, m[1]) * inv_rhoK;
+        A.uout[A.unn + own] = fmad(C(0.5), K * Fy, m[2]) * inv_rhoK;
+        A.uout[2 * A.unn + own] = fmad(C(0.5), K * Fz, m[3]) * inv_rhoK;
+    };
+
     // Software pipeline over the planes of the chunk.  At iteration z the
     // states of plane z (collision) and z+1 (moments) are in registers.  The
     // loads of the tile node of plane z+2 are issued right after the moments
@@ -1224,7 +1258,10 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
             if (!LATE_HALO && has_halo) load_node(hrow, zoff2, nqh);
         }
         __syncthreads();
-        if (active) collide_stream(z, s, cur, c_rho, c_T, c_psi);
+        if (active) {
+            if constexpr (VEL) velocity_out(z, s, cur, c_rho, c_psi);
+            else collide_stream(z, s, cur, c_rho, c_T, c_psi);
+        }
         cur = nxt;
         nxt = nq;
         if constexpr (LATE_HALO) {
@@ -1237,7 +1274,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         c_psi = n_psi;
     }
 
-    if (P.gravity) {
+    if (!VEL && P.gravity) {
         // Deterministic per-workgroup partial sum of rho(t) for rho_ave.
         for (int o = 32; o > 0; o >>= 1) rho_sum += __shfl_xor(rho_sum, o, 64);
         if ((tid & 63) == 0) s_red[tid >> 6] = rho_sum;
@@ -1254,6 +1291,13 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
 template <typename ST, int TX, int TY, bool WALLS, bool BUF, bool DFD>
 __global__ void __launch_bounds__(TX *TY) k_step(const StepArgs<ST> A) {
     step_tile<ST, TX, TY, WALLS, BUF, DFD>(A, xcd_logical_block(blockIdx.x, gridDim.x), blockIdx.x);
+}
+
+// The velocity pass that precedes a step with the finite-difference
+// divergence: u(t) of every node into A.uout.
+template <typename ST, int TX, int TY, bool WALLS, bool BUF>
+__global__ void __launch_bounds__(TX *TY) k_velocity_pass(const StepArgs<ST> A) {
+    step_tile<ST, TX, TY, WALLS, BUF, false, true>(A, xcd_logical_block(blockIdx.x, gridDim.x), blockIdx.x);
 }
 
 // Work list of a batch of independent lattices advanced by one launch.

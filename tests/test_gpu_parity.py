@@ -306,29 +306,20 @@ def test_fd_divergence_against_oracle(storage, case):
         assert e["rho"] <= tol and e["T"] <= tol and e["u_l2"] <= 20 * tol, e
 
 
-def test_fd_divergence_launch_shapes():
-    """Every launch shape whose LDS fits gives the same bits; one that does not
-    fit is refused with EINVAL, not run."""
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_fd_divergence_launch_shapes(storage):
+    """The velocity pass and the step share the launch shape; every shape
+    gives the same bits."""
     from paper_2201_06039_amd import lbm
     w = workload("evaporation_128", nx=40, ny=36, nz=20, radius=7.0, divu_mode=1)
     outs = []
-    for launch in [(64, 4, 4), (32, 8, 7), (64, 4, 20), (32, 8, 1)]:
-        _say(f"FD divergence f32 launch {launch}")
-        outs.append(run_gpu(w, 25, "f32", launch=launch))
+    for launch in [(64, 4, 4), (32, 8, 7), (128, 4, 20), (64, 8, 1), (32, 16, 6)]:
+        _say(f"FD divergence {storage} launch {launch}")
+        outs.append(run_gpu(w, 25, storage, launch=launch))
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
             assert np.array_equal(a, b)
-    for launch in [(128, 4, 8), (64, 8, 8)]:
-        _say(f"FD divergence f16 launch {launch}")
-        try:
-            o = run_gpu(w, 25, "f16", launch=launch)
-        except lbm.LbmError as exc:
-            assert exc.status == lbm.EINVAL, exc
-            continue
-        ref = run_gpu(w, 25, "f16", launch=(64, 4, 8))
-        for a, b in zip(ref, o):
-            assert np.array_equal(a, b)
     lat = lbm.Lattice(w["params"], storage="f32", device="cuda:0")
-    assert lat.launches_per_step() == 3
+    assert lat.launches_per_step() == 2
     lat.close()
 
