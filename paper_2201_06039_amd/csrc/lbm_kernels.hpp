@@ -39,10 +39,16 @@ namespace lbm {
 constexpr int kE19X[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
 constexpr int kE19Y[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
 constexpr int kE19Z[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
-// Sec. III B, Eq. (21): D3Q7 velocity components.
-constexpr int kE7X[7] = {0, 1, -1, 0, 0, 0, 0};
-constexpr int kE7Y[7] = {0, 0, 0, 1, -1, 0, 0};
-constexpr int kE7Z[7] = {0, 0, 0, 0, 0, 1, -1};
+// Sec. III B, Eq. (21): the D3Q7 velocities are the first seven of Eq. (2)
+// in the same order, so the temperature lattice (D3Q7 or D3Q19) indexes
+// kE19* directly.
+constexpr bool d3q7_is_head_of_d3q19() {
+    constexpr int e7[7][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+    for (int a = 0; a < 7; ++a)
+        if (e7[a][0] != kE19X[a] || e7[a][1] != kE19Y[a] || e7[a][2] != kE19Z[a]) return false;
+    return true;
+}
+static_assert(d3q7_is_head_of_d3q19(), "D3Q7 velocity order");
 
 __host__ __device__ constexpr int opposite(int a) { return a == 0 ? 0 : ((a & 1) ? a + 1 : a - 1); }
 
@@ -753,6 +759,14 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
             }
         }
     };
+    // Plane buffers of the software pipeline (below): plane z, plane z+1
+    // (tile, halo node), plane z+2 (tile node; halo node where it is loaded
+    // before the barrier).  Where the loads of the halo node of plane z+2 are
+    // issued (measured per format and lattice, see the pipeline):
+    //   1: inside the collision of plane z, before its streaming stores;
+    //   2: after the collision (FP16 with the D3Q19 temperature lattice).
+    Node cur, nxt, nxh, nq;
+    constexpr int HALO_AT = (QT == 19 && sizeof(E) == 2) ? 2 : 1;
     // State of plane zp for this thread's tile node and its halo node.
     auto load_plane = [&](int zp, Node &k, Node &h) {
         const unsigned zoff = (unsigned)zmap(zp) * plane;
@@ -1037,6 +1051,10 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
             *phi_own = phis;
         }
 
+        if constexpr (HALO_AT == 1) {
+            // the halo node of plane z+2 (nxh was consumed by the moments of z+1)
+            if (z + 2 <= zend && has_halo) load_node(hrow, (unsigned)zmap(z + 2) * plane, nxh);
+        }
         // ---- streaming (push), Eq. (4) and Eq. (40) ----
         const unsigned PB = plane * NS;
         const unsigned Zc = (unsigned)z * PB;
@@ -1225,15 +1243,14 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     // states of plane z (collision) and z+1 (moments) are in registers.  The
     // loads of the tile node of plane z+2 are issued right after the moments
     // of z+1, so that their latency overlaps the barrier and the collision of
-    // plane z.  The loads of its halo node go with them for 4-byte D3Q7
-    // storage; for 16-bit storage and the D3Q19 temperature lattice they
-    // follow the collision, so that the halo words are not held across it
-    // (measured: FP16 4% faster at 128^3 and 7% at 256^3, D3Q19 9-12%; plain
-    // FP32 4% slower at 256^3).  Issuing loads earlier would put more memory
-    // operations between a load and its use than the vmcnt counter can
-    // express, which forces a full drain.
-    constexpr bool LATE_HALO = sizeof(E) == 2 || QT == 19;
-    Node cur, nxt, nxh, nq, nqh;  // plane z; plane z+1 (tile, halo); plane z+2 (tile, halo)
+    // plane z.  The loads of its halo node are issued inside the collision,
+    // before the streaming stores, so that the halo words are not held across
+    // the whole collision (HALO_AT above).  Against issuing them with the tile
+    // loads (measured, 128^3 / 256^3 evaporation): FP16 +5% / +19%, FP32 +6% /
+    // same, BF16 +9%; FP16 with the D3Q19 temperature lattice runs best with
+    // them after the collision (+11%; inside it: +3%).  Issuing loads earlier
+    // would put more memory operations between a load and its use than the
+    // vmcnt counter can express, which forces a full drain.
     C c_rho, c_T, c_psi, n_rho, n_T, n_psi;
     {
         Node t0, th0, h0;
@@ -1253,10 +1270,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         plane_moments((s + 1) & 3, nxt, nxh, n_rho, n_T, n_psi);
         if constexpr (DFD) plane_velocity((s + 1) & 3, z + 1);
         const unsigned zoff2 = (unsigned)zmap(z + 2) * plane;
-        if (z + 2 <= zend) {
-            load_node(irow, zoff2, nq);
-            if (!LATE_HALO && has_halo) load_node(hrow, zoff2, nqh);
-        }
+        if (z + 2 <= zend) load_node(irow, zoff2, nq);
         __syncthreads();
         if (active) {
             if constexpr (VEL) velocity_out(z, s, cur, c_rho, c_psi);
@@ -1264,11 +1278,9 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         }
         cur = nxt;
         nxt = nq;
-        if constexpr (LATE_HALO) {
-            if (z + 2 <= zend && has_halo) load_node(hrow, zoff2, nxh);
-        } else {
-            nxh = nqh;
-        }
+        // Halo loads not issued inside a collision: inactive tile threads,
+        // the velocity pass, and HALO_AT == 2.
+        if ((HALO_AT == 2 || VEL || !active) && z + 2 <= zend && has_halo) load_node(hrow, zoff2, nxh);
         c_rho = n_rho;
         c_T = n_T;
         c_psi = n_psi;
