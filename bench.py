@@ -3,7 +3,8 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                     [--storage f16|f32|f64|bf16|f32dev] [--compare f32|none]
                     [--thermal-lattice d3q7|d3q19] [--divu local|fd] [--tile TXxTY] [--chunk CZ]
-                    [--no-precision] [--no-batch] [--no-lattice-comparison] [--no-cpu-baseline]
+                    [--no-precision] [--no-batch] [--no-lattice-comparison] [--no-workloads]
+                    [--workloads NAME,...] [--no-cpu-baseline]
 
 One step = one fused time step of the whole grid (both lattices, streaming and
 boundary rules) on synthetic seeded input already resident in HBM.  Prints one
@@ -14,8 +15,8 @@ storage format against the FP64 oracle's reference values (coexistence
 densities, Laplace jump, D^2 slope), the batched step over 256 independent
 lattices of uneven size (aggregate MLUPS after autotuning), the same step with
 a D3Q19 temperature lattice against the D3Q7 one (the paper's efficiency
-argument for D3Q7, Sec. III B), and the FP64 oracle timed on the host as a
-CPU baseline.
+argument for D3Q7, Sec. III B), the rates on the pool-boiling wall grid, and
+the FP64 oracle timed on the host as a CPU baseline.
 """
 import argparse
 import hashlib
@@ -178,6 +179,29 @@ def batch_run(storage, steps, warmup, name="batch_256", launch=None):
             "thread_slot_efficiency": round(nodes / slots, 4), "graph": True}
 
 
+def other_workloads(lbm, W, names, steps, warmup, storages=("f16", "f32")):
+    """MLUPS and roofline fraction of the step on further workloads (the
+    pool-boiling wall grid by default; its step adds the rho_ave reduction
+    launch, which the fraction counts)."""
+    out = {}
+    for name in names:
+        w = W.load(name)
+        fields = W.fields(w)
+        p = w["params"]
+        nn = p["nx"] * p["ny"] * p["nz"]
+        row = {"grid": [p["nx"], p["ny"], p["nz"]]}
+        for storage in storages:
+            ms, launch, launches = timed_run(lbm, p, fields, storage, steps, warmup)
+            sec = ms / 1e3 / steps
+            row[storage] = {"MLUPS": round(nn / sec / 1e6, 2), "ms_per_step": round(ms / steps, 5),
+                            "roofline_frac": round(bytes_per_lup(storage) * nn / sec / 1e9 / HBM_PEAK_GBS, 4),
+                            "launches_per_step": launches, "tile": [launch["tile_x"], launch["tile_y"]],
+                            "chunk_z": launch["chunk_z"]}
+            print(f"# {name} {storage}: {ms / steps:.5f} ms/step", file=sys.stderr, flush=True)
+        out[name] = row
+    return out
+
+
 def lattice_comparison(lbm, p, fields, steps, warmup, storages=("f16", "f32")):
     """The step with the D3Q7 and the D3Q19 temperature lattice, both with the
     BGK collision of Eq. (19) (the only one the paper specifies for both), on
@@ -240,6 +264,9 @@ def main():
                     help="fixed batch launch (tile, chunk, workgroups) instead of the autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lattice-comparison", action="store_true")
+    ap.add_argument("--no-workloads", action="store_true", help="skip the other-workload leg")
+    ap.add_argument("--workloads", default="pool_boiling_256x256x384",
+                    help="comma-separated workloads timed in the other-workload leg")
     ap.add_argument("--divu", default="local", choices=["local", "fd"],
                     help="velocity divergence of the timed step: Eq. (48) or finite differences")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
@@ -340,6 +367,8 @@ def main():
         out["temperature_lattice_comparison"] = lattice_comparison(lbm, p, fields, max(1, args.steps // 2),
                                                                    args.warmup)
         out["divergence_comparison"] = divergence_comparison(lbm, p, fields, max(1, args.steps // 4), args.warmup)
+    if not args.no_workloads and not q19t and not fd and args.workloads:
+        out["workloads"] = other_workloads(lbm, W, args.workloads.split(","), 200, 10)
     if not args.no_precision and not q19t and not fd:
         errs = precision_errors(args.storage)
         print(f"# precision of {args.storage}: {errs}", file=sys.stderr, flush=True)
