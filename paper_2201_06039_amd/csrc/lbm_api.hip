@@ -265,22 +265,19 @@ namespace {
 
 int hip_status(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EHIP; }
 
-// Default launch shape (measured on MI355X): tiles as wide as the rows allow
-// (128 nodes: whole 512-byte rows, and the x halo wraps inside the tile when
-// nx = 128), 4 rows, and chunks of 16-32 planes; the z halo of a chunk is read
-// twice, so chunks are kept long unless the grid would then give fewer
-// workgroups than the 256 compute units.
+// Default launch shape (measured on MI355X): 64x8 tiles where the rows are
+// long enough (their halo is 29% of the tile against 52% for 128x4 or 64x4;
+// FP32 at 128^3 / 192^3 / 256^3 / the 256x256x384 pool: 1-13% faster than
+// 128x4 tiles, FP16 2-4% faster than 32x16 except at 128^3), and chunks of
+// 16-32 planes; the z halo of a chunk is read twice, so chunks are kept long
+// unless the grid would then give fewer workgroups than the 256 compute
+// units.
 void set_default_launch(lbm_handle *h) {
     const int nx = h->p.nx, ny = h->p.ny, nz = h->p.nz;
     const bool half = h->L.es == 2;
-    if (half && nx >= 64) {
-        // 16-bit storage: the kernel is bound by instruction issue more than
-        // by the row length, and 64x8 tiles recompute fewer halo nodes.
+    if (nx >= 64) {
         h->tile_x = 64;
         h->tile_y = 8;
-    } else if (nx >= 96) {
-        h->tile_x = 128;
-        h->tile_y = 4;
     } else if (nx > 32) {
         h->tile_x = 64;
         h->tile_y = 4;
