@@ -202,6 +202,50 @@ def other_workloads(lbm, W, names, steps, warmup, storages=("f16", "f32")):
     return out
 
 
+def d2_full(lbm, W, storages=("f64", "f32", "f32dev", "f16", "bf16"), steps=60000, every=1000):
+    """The D^2 test at the size the paper states (Sec. IV A: 100^3, D_0 = 50)
+    for `steps` steps in every storage format: (D/D_0)^2 read out every
+    `every` steps, and the slope of each window against that of the FP64
+    kernel (and of the FP64 oracle, where tests/golden/d2_full_oracle.json
+    holds its values)."""
+    import numpy as np
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import precision_metrics as PM
+    w = W.load("d2_law_100")
+    fields = W.fields(w)
+    times = np.arange(every, steps + 1, every)
+    curves = {}
+    for storage in storages:
+        lat = lbm.Lattice(w["params"], storage=storage, device="cuda:0")
+        lat.init_fields(*fields)
+        d2 = []
+        for _ in times:
+            lat.step(every)
+            d2.append(PM.d2_ratio(lat.rho_u_T()[0], w))
+        lat.close()
+        curves[storage] = np.array(d2)
+        print(f"# d2_full {storage}: d2(end) = {d2[-1]:.5f}", file=sys.stderr, flush=True)
+    ref_path = os.path.join(ROOT, "tests", "golden", "d2_full_oracle.json")
+    if os.path.exists(ref_path):
+        with open(ref_path) as fh:
+            ref = json.load(fh)
+        if ref["times"] == [int(t) for t in times]:
+            curves["oracle"] = np.array(ref["d2"])
+    windows = [(w0, w1) for w0, w1 in ((5000, 10000), (10000, 20000), (20000, 40000), (40000, 60000)) if w1 <= steps]
+    out = {"workload": "d2_law_100", "steps": steps, "every": every, "slope_relative_error": {}, "d2_end": {}}
+    for name, c in curves.items():
+        out["d2_end"][name] = round(float(c[-1]), 6)
+    base = "oracle" if "oracle" in curves else "f64"
+    out["reference"] = base
+    for w0, w1 in windows:
+        sel = (times >= w0) & (times <= w1)
+        ref_slope = np.polyfit(times[sel], curves[base][sel], 1)[0]
+        out["slope_relative_error"][f"{w0}-{w1}"] = {
+            name: round(float((np.polyfit(times[sel], c[sel], 1)[0] - ref_slope) / abs(ref_slope)), 5)
+            for name, c in curves.items() if name != base}
+    return out
+
+
 def lattice_comparison(lbm, p, fields, steps, warmup, storages=("f16", "f32")):
     """The step with the D3Q7 and the D3Q19 temperature lattice, both with the
     BGK collision of Eq. (19) (the only one the paper specifies for both), on
@@ -265,6 +309,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lattice-comparison", action="store_true")
     ap.add_argument("--no-workloads", action="store_true", help="skip the other-workload leg")
+    ap.add_argument("--d2-full", action="store_true",
+                    help="only run the D^2 test at 100^3 for 60000 steps in every storage format (about 40 s) "
+                         "and print its JSON")
     ap.add_argument("--workloads", default="pool_boiling_256x256x384",
                     help="comma-separated workloads timed in the other-workload leg")
     ap.add_argument("--divu", default="local", choices=["local", "fd"],
@@ -299,6 +346,10 @@ def main():
         return
 
     from paper_2201_06039_amd import lbm, workloads as W
+
+    if args.d2_full:
+        print(json.dumps(d2_full(lbm, W)), flush=True)
+        return
 
     if args.batch_only:
         bl = tuple(int(v) for v in args.batch_launch.split("x")) if args.batch_launch else None
