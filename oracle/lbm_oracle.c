@@ -57,6 +57,9 @@ typedef struct orc_params {
     int thermal_lattice;   /* 0: D3Q7 (Sec. III B); 1: D3Q19 with the standard weights, BGK only */
     int divu_mode;         /* 0: Eq. (48) at every node; 1: isotropic finite differences of u at
                               interior nodes, Eq. (48) at the layers next to a wall or the open top */
+    int freeze_flow;       /* pin hook only (no counterpart in the product): 1 keeps the density
+                              populations fixed and takes u = 0 and div u = 0 in Eq. (18), so the
+                              temperature lattice evolves by conduction through a frozen rho(x) */
 } orc_params;
 
 typedef struct orc_sim {
@@ -432,6 +435,8 @@ static void pass_collide(orc_sim *s) {
         double F[3], Fm[3], u[3];
         total_force(s, i, F, Fm);
         velocity(s, i, F, u);
+        if (p->freeze_flow)
+            for (int c = 0; c < 3; ++c) u[c] = 0.0;
 
         /* Eq. (3): m* = m - Lambda (m - m_eq) + dt (I - Lambda/2) S. */
         double fl[Q19], m[Q19], meq[Q19], S[Q19], ms[Q19];
@@ -480,6 +485,7 @@ static void pass_collide(orc_sim *s) {
                 divu = acc;
             }
         }
+        if (p->freeze_flow) divu = 0.0;
 
         const double T = s->T[i];
         /* chi = lambda/(rho cV) (constant lambda) or given; chi = (vs_T - 0.5) c_sT^2 dt. */
@@ -566,7 +572,7 @@ static void pass_stream(orc_sim *s) {
         for (int y = 0; y < p->ny; ++y)
             for (int x = 0; x < p->nx; ++x) {
                 const long i = node_index(p, x, y, z);
-                for (int a = 0; a < Q19; ++a) {
+                for (int a = 0; a < Q19 && !p->freeze_flow; ++a) {
                     const int xd = ((x + E19[a][0]) % p->nx + p->nx) % p->nx;
                     const int yd = ((y + E19[a][1]) % p->ny + p->ny) % p->ny;
                     int zd = z + E19[a][2];
@@ -605,7 +611,7 @@ static void pass_stream(orc_sim *s) {
                     if (in_shell(p, x, y, z))
                         for (int a = 0; a < s->QT; ++a) s->gn[a * nn + node_index(p, x, y, z)] = s->wT[a] * p->T_shell;
     }
-    if (walls) {
+    if (walls && !p->freeze_flow) {
         const int zt = p->nz - 1;
         for (int y = 0; y < p->ny; ++y)
             for (int x = 0; x < p->nx; ++x)
@@ -613,7 +619,8 @@ static void pass_stream(orc_sim *s) {
                     if (E19[a][2] < 0)
                         s->fn[a * nn + node_index(p, x, y, zt)] = s->fn[a * nn + node_index(p, x, y, zt - 1)];
     }
-    double *t = s->f; s->f = s->fn; s->fn = t;
+    double *t;
+    if (!p->freeze_flow) { t = s->f; s->f = s->fn; s->fn = t; }
     if (p->thermal) { t = s->g; s->g = s->gn; s->gn = t; }
 }
 

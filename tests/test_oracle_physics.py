@@ -310,6 +310,137 @@ def test_wall_conduction_profile(oracle_lib):
     np.testing.assert_allclose((T - Tt) / (Tw - Tt), (expect - Tt) / (Tw - Tt), atol=2e-3)
 
 
+def _frozen_layer_profile(oracle_lib, kappa_mode, kappa, steps=60000, nz=32):
+    """Steady temperature between the anti-bounce-back wall (T_w at z = -1/2)
+    and the open top (T_t at z = nz - 1/2) through a density layer held fixed
+    (the oracle's freeze_flow hook: u = 0, div u = 0).  rho(z) rises smoothly
+    from 1 to 2 across the middle of the column."""
+    z = np.arange(nz, dtype=float)
+    prof = lambda q: 1.0 + 0.5 * (1.0 + np.tanh((q - nz / 2) / 4.0))
+    rho = prof(z).reshape(nz, 1, 1)
+    ones = np.ones((nz, 1, 1))
+    Tw, Tt = 1.1, 1.0
+    s = oracle_lib.Sim(nx=1, ny=1, nz=nz, bc_z=1, a=0.0, b=0.0, R=0.0, cV=5.0, kappa_mode=kappa_mode,
+                       kappa=kappa, T_wall_patch=Tw, T_wall=Tw, T_top=Tt, patch_radius=0.0, freeze_flow=1)
+    s.init_fields(rho, 0 * ones, 0 * ones, 0 * ones, Tt * ones)
+    s.step(steps)
+    r, _, _, _, T = s.rho_u_T()
+    np.testing.assert_allclose(r.reshape(nz), prof(z), rtol=1e-12)  # the layer did not move
+
+    def integral(fn):
+        # int_{-1/2}^{z} fn(rho(q)) dq on a fine midpoint grid (exact to ~1e-8 here)
+        q = np.linspace(-0.5, nz - 0.5, 64 * nz + 1)
+        qm = 0.5 * (q[1:] + q[:-1])
+        cum = np.concatenate([[0.0], np.cumsum(fn(prof(qm)) * np.diff(q))])
+        return np.interp(z, q, cum), cum[-1]
+
+    return z, (T.reshape(nz) - Tt) / (Tw - Tt), integral
+
+
+def test_conduction_through_density_layer_constant_chi(oracle_lib):
+    """Eq. (17)-(18) at rest with constant chi: dT/dt = div(chi grad T) +
+    chi grad(rho c_V) . grad T / (rho c_V) = (chi / rho) div(rho grad T), so the
+    steady flux rho dT/dz is uniform: T(z) - T_w is proportional to
+    int dz / rho.  Dropping the grad(rho c_V) term gives a linear profile, a
+    flipped sign gives dT/dz proportional to rho, a c_V kept on one side only
+    scales the term by 5: each misses by more than 0.05 of T_w - T_t."""
+    z, theta, integral = _frozen_layer_profile(oracle_lib, kappa_mode=1, kappa=0.1)
+    I, Itot = integral(lambda r: 1.0 / r)
+    expect = 1.0 - I / Itot
+    np.testing.assert_allclose(theta, expect, atol=2e-3)
+    linear = 1.0 - (z + 0.5) / len(z)
+    assert np.abs(theta - linear).max() > 0.05
+
+
+def test_conduction_through_density_layer_constant_lambda(oracle_lib):
+    """Eq. (17)-(18) at rest with constant lambda (chi = lambda/(rho c_V), the
+    D^2-test mode): rho c_V dT/dt = lambda lap T, so the steady profile is
+    linear however rho varies.  Without the grad(rho c_V) term the flux
+    chi dT/dz would be uniform instead (dT/dz proportional to rho); with its
+    sign flipped dT/dz goes as rho^2."""
+    z, theta, integral = _frozen_layer_profile(oracle_lib, kappa_mode=0, kappa=0.5)
+    linear = 1.0 - (z + 0.5) / len(z)
+    np.testing.assert_allclose(theta, linear, atol=2e-3)
+    J, Jtot = integral(lambda r: r)
+    assert np.abs(theta - (1.0 - J / Jtot)).max() > 0.05
+
+
+def _layered_with_gravity(oracle_lib, **kw):
+    Tc, T, rl, rg = coexistence()
+    W = workloads()
+    nz, g = 96, -2e-5
+    fields = W.flat_interface(2, 2, nz, rl, rg, T, width=4.0, liquid_fraction=0.5)
+    p = dict(nx=2, ny=2, nz=nz, sigma=sigma_default(), thermal=0, grav=(0.0, 0.0, g), kappa_mode=1, kappa=0.08)
+    p.update(kw)
+    s = oracle_lib.Sim(**p)
+    s.init_fields(*fields)
+    return s, fields[0], g
+
+
+def test_buoyancy_accelerates_bulk_phases(oracle_lib):
+    """F_b = (rho - rho_ave) g (Sec. IV C) with Eq. (10) and the momentum
+    change F per step of the forcing scheme: in the middle of each bulk phase
+    of a layered periodic column (F_m = 0 there), before pressure waves from
+    the interfaces arrive, the readout velocity after n steps is
+    (n + 1/2)(rho - rho_ave) g / rho, with rho_ave the mean density.  The
+    liquid sinks and the vapour rises.  A flipped sign, a missing F/2, or
+    rho g in place of (rho - rho_ave) g all fail."""
+    s, rho0, g = _layered_with_gravity(oracle_lib)
+    ra = rho0.mean()
+    assert s.rho_ave == pytest.approx(ra, rel=1e-14)
+    nz = rho0.shape[0]
+    liquid, vapour = nz // 2, 0
+    for n in range(0, 10):
+        r, _, _, uz, _ = s.rho_u_T()
+        for zc in (liquid, vapour):
+            rr = r[zc, 0, 0]
+            expect = (n + 0.5) * (rr - ra) * g / rr
+            assert uz[zc, 0, 0] == pytest.approx(expect, rel=1e-5), (n, zc)
+        assert uz[liquid, 0, 0] < 0 < uz[vapour, 0, 0]  # g points down: the lighter phase rises
+        s.step(1)
+
+
+def test_buoyancy_uses_the_mean_density_one_step_back(oracle_lib):
+    """rho_ave of step t is the mean density at t - 1 (reading: the GPU takes
+    it from the previous step's reduction), carried in the state.  (1) A step
+    uses the carried value, not the current mean: restarting the layered
+    column with rho_ave set to X, one step gives the bulk velocity
+    ((rho - X) + (rho - mean)/2) g / rho (the step's F with X, the readout's
+    F/2 with the mean now carried).  (2) With the open top, mass is not
+    conserved, and after every step the carried rho_ave equals the mean of the
+    density read out one step earlier."""
+    s, rho0, g = _layered_with_gravity(oracle_lib)
+    mean = rho0.mean()
+    st = s.state()
+    X = 0.5 * mean
+    s.set_state(st["f"], st["g"], st["phi_prev"], X)
+    s.step(1)
+    r, _, _, uz, _ = s.rho_u_T()
+    assert s.rho_ave == pytest.approx(mean, rel=1e-14)
+    nz = rho0.shape[0]
+    for zc in (nz // 2, 0):
+        rr = r[zc, 0, 0]
+        expect = ((rr - X) + 0.5 * (rr - mean)) * g / rr
+        assert uz[zc, 0, 0] == pytest.approx(expect, rel=1e-5), zc
+
+    Tc, T, rl, rg = coexistence()
+    W = workloads()
+    p = dict(nx=6, ny=5, nz=24, bc_z=1, sigma=sigma_default(), kappa_mode=1, kappa=0.08,
+             grav=(0, 0, -2e-5), T_wall_patch=0.95 * Tc, T_wall=T, T_top=T, patch_radius=2.0)
+    s = oracle_lib.Sim(**p)
+    s.init_fields(*W.pool(6, 5, 24, 8.0, rl, rg, T, width=4.0, noise=1e-4, seed=2))
+    prev = s.rho_u_T()[0].mean()
+    assert s.rho_ave == pytest.approx(prev, rel=1e-14)
+    moved = 0.0
+    for _ in range(40):
+        s.step(1)
+        now = s.rho_u_T()[0].mean()
+        assert s.rho_ave == pytest.approx(prev, rel=1e-13, abs=0)
+        moved = max(moved, abs(now - prev) / prev)
+        prev = now
+    assert moved > 1e-9  # the open top changes the mass, so the lag matters
+
+
 def test_reservoir_layer_is_a_dirichlet_boundary(oracle_lib):
     """Constant-temperature boundary of the D^2 test (Sec. IV A): the outer
     layer of an L^3 box is held at T_s.  The layer's temperature stays T_s
