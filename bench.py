@@ -3,25 +3,29 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                     [--storage f16|f32|f64|bf16|f32dev] [--compare f32|none]
                     [--thermal-lattice d3q7|d3q19] [--divu local|fd] [--tile TXxTY] [--chunk CZ]
-                    [--no-precision] [--no-batch] [--no-lattice-comparison] [--no-workloads]
-                    [--workloads NAME,...] [--no-cpu-baseline]
+                    [--no-precision] [--no-d2-full-size] [--no-batch] [--no-lattice-comparison]
+                    [--no-workloads] [--workloads NAME,...] [--no-cpu-baseline]
 
 One step = one fused time step of the whole grid (both lattices, streaming and
-boundary rules) on synthetic seeded input already resident in HBM.  Prints one
+boundary rules) on synthetic seeded input already resident in HBM.  The
+headline workload is the precision form of the method: a 512^3 periodic
+field of 64 droplets at T_sat (Sec. IV A parameters) with FP16 deviation
+storage, against the same grid with FP32 population storage.  Prints one
 JSON line: MLUPS (million lattice-node updates per second) of the chosen
-population storage (FP16 deviations by default), the HBM roofline of the step
-kernel, the same step with FP32 storage for comparison, the errors of the
-storage format against the FP64 oracle's reference values (coexistence
-densities, Laplace jump, D^2 slope), the batched step over 256 independent
-lattices of uneven size (aggregate MLUPS after autotuning), the same step with
-a D3Q19 temperature lattice against the D3Q7 one (the paper's efficiency
-argument for D3Q7, Sec. III B), the rates on the pool-boiling wall grid, and
-the FP64 oracle timed on the host as a CPU baseline.
+storage, the HBM roofline of the step kernel at the method's algorithmic
+bytes per update, the FP32-storage comparison, the errors of the storage
+format against the FP64 oracle (coexistence densities, Laplace jump, D^2
+slope, each case labelled with its grid and window, and the D^2 test at the
+paper's 100^3 size), the batched step over 256 independent lattices of uneven
+size, the D3Q19-vs-D3Q7 temperature lattice and finite-difference-vs-Eq. (48)
+comparisons and the 128^3 and pool-boiling rates, a streaming-copy ceiling,
+and the FP64 oracle timed on the host cores as a CPU baseline.
 """
 import argparse
 import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -30,20 +34,26 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS (D3Q19+D3Q7 fused step) + % HBM peak, FP16-store vs FP32 at stated error"
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes per lattice update: 19 + 7 populations (plus the two
-# reference values rho_r, T_r of the deviation formats: FP16 for f16, FP32
-# for bf16 and f32dev) and the FP32 phi_s history (FP64 for f64), each read
-# once and written once.
-BYTES_PER_LUP = {"f32": 2 * 26 * 4 + 8, "f64": 2 * 26 * 8 + 16, "f16": 2 * (26 * 2 + 2 * 2) + 8,
-                 "bf16": 2 * (26 * 2 + 2 * 4) + 8, "f32dev": 2 * 28 * 4 + 8}
-# The same with a D3Q19 temperature lattice: 19 + 19 populations.
-BYTES_PER_LUP_Q19T = {"f32": 2 * 38 * 4 + 8, "f64": 2 * 38 * 8 + 16, "f16": 2 * (38 * 2 + 2 * 2) + 8}
+# Algorithmic bytes per lattice update: the state the method must move, each
+# value read once and written once -- 19 + 7 populations and the phi_s
+# history of Eq. (23) (FP32; FP64 for f64).  FP16/BF16 populations: 112 B;
+# FP32: 216 B (FP32 deviations move FP32 populations too).
+BYTES_ALG = {"f32": 2 * 26 * 4 + 8, "f64": 2 * 26 * 8 + 16, "f16": 2 * 26 * 2 + 8, "bf16": 2 * 26 * 2 + 8,
+             "f32dev": 2 * 26 * 4 + 8}
+# What the deviation formats move in addition: the per-node references
+# rho_r, T_r (FP16 for f16, FP32 for bf16 and f32dev), read and written.
+BYTES_WITH_REFERENCES = {"f32": 216, "f64": 432, "f16": 120, "bf16": 128, "f32dev": 232}
+# The same with a D3Q19 temperature lattice (19 + 19 populations).
+BYTES_ALG_Q19T = {"f32": 2 * 38 * 4 + 8, "f64": 2 * 38 * 8 + 16, "f16": 2 * 38 * 2 + 8}
 
 
-def bytes_per_lup(storage, q19t=False):
-    return (BYTES_PER_LUP_Q19T if q19t else BYTES_PER_LUP)[storage]
+def bytes_alg(storage, q19t=False):
+    return (BYTES_ALG_Q19T if q19t else BYTES_ALG)[storage]
+
+
 PRECISION_BOUND = 1e-3
-KERNEL_SOURCES = ["paper_2201_06039_amd/csrc/lbm_kernels.hpp", "paper_2201_06039_amd/csrc/lbm_api.hip"]
+# Device code of the step kernels: counter figures stay valid while it is unchanged.
+KERNEL_SOURCES = ["paper_2201_06039_amd/csrc/lbm_kernels.hpp"]
 
 
 def traffic_file(workload, storage, q19t=False):
@@ -74,32 +84,59 @@ def measured_traffic(workload, storage, launch, q19t=False):
     return t.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(params, fields, seconds=15.0):
-    """The FP64 oracle on the host cores, on the same workload, for a bounded
-    number of steps sized to take about `seconds`."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(w, fields, slab_all=64, slab_one=8):
+    """The FP64 oracle (as it stands) on the host cores, on bounded samples of
+    the same workload: 2 steps of the z-slab [0, slab_all) of the grid with
+    every thread OpenMP gives it, and 1 step of the slab [0, slab_one) on one
+    thread.  Each slab is a periodic box of its own (the per-node work of the
+    oracle does not depend on the data)."""
     from oracle import sim
-    s = sim.Sim(**params)
-    s.init_fields(*fields)
-    t0 = time.perf_counter()
-    s.step(1)
-    t1 = time.perf_counter()
-    per = max(t1 - t0, 1e-3)
-    n = max(1, int(seconds / per) - 1)
-    t0 = time.perf_counter()
-    s.step(n)
-    t1 = time.perf_counter()
-    nn = s.nn
-    s.close()
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(nn * n / (t1 - t0) / 1e6, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"{n} steps of the full {params['nx']}x{params['ny']}x{params['nz']} grid "
-                      f"after 1 untimed step, FP64 C + OpenMP"}
+    p = dict(w["params"])
+    out = {}
+    for name, nz, steps, threads in (("all", slab_all, 2, None), ("one", slab_one, 1, 1)):
+        nz = min(nz, p["nz"])
+        sl = [f[:nz] for f in fields]
+        if threads:
+            sim.set_threads(threads)
+        s = sim.Sim(**dict(p, nz=nz))
+        s.init_fields(*sl)
+        t0 = time.perf_counter()
+        s.step(steps)
+        t1 = time.perf_counter()
+        used = sim.max_threads()
+        s.close()
+        if threads:
+            sim.set_threads(0)
+        out[name] = dict(value=round(s.nn * steps / (t1 - t0) / 1e6, 3), cores=used,
+                         sample=f"{steps} step(s) of the {p['nx']}x{p['ny']}x{nz} slab z < {nz} of the "
+                                f"{p['nx']}x{p['ny']}x{p['nz']} field, FP64 C + OpenMP, {used} thread(s)")
+    return {"value": out["all"]["value"], "unit": "MLUPS", "cores": out["all"]["cores"], "kind": "oracle",
+            "sample": out["all"]["sample"], "single_thread": out["one"], "cpu_model": cpu_model()}
 
 
-def timed_run(lbm, p, fields, storage, steps, warmup, tile=None, chunk=None):
-    """Warm up, then time `steps` steps with HIP events on the library's stream."""
+def new_stream():
     import torch
-    lat = lbm.Lattice(p, storage=storage, device="cuda:0")
+    return torch.cuda.Stream(device="cuda:0")  # default priority
+
+
+def timed_run(lbm, p, fields, storage, steps, warmup, tile=None, chunk=None, repeats=1):
+    """Warm up, then time `steps` steps with HIP events on the library's stream
+    (its own stream, so pairs of steps replay a captured graph).  With
+    repeats > 1 the K-step timing is repeated and every repetition kept; the
+    first is the reported one."""
+    import torch
+    lat = lbm.Lattice(p, storage=storage, device="cuda:0", stream=new_stream())
     if tile or chunk:
         cur = lat.launch()
         tx, ty = (int(v) for v in tile.split("x")) if tile else (cur["tile_x"], cur["tile_y"])
@@ -107,23 +144,45 @@ def timed_run(lbm, p, fields, storage, steps, warmup, tile=None, chunk=None):
     launch = lat.launch()
     lat.init_fields(*fields)
     lat.step(warmup)
-    torch.cuda.synchronize()
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record(lat.stream)
-    lat.step(steps)
-    end.record(lat.stream)
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(end)
+    times = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(lat.stream)
+        lat.step(steps)
+        end.record(lat.stream)
+        torch.cuda.synchronize()
+        times.append(start.elapsed_time(end))
     lat.rho_u_T()  # raises if any step was unstable
     launches = lat.launches_per_step()
     lat.close()
-    return ms, launch, launches
+    return times[0], launch, launches, times
+
+
+def copy_ceiling(lbm, mbytes=2048, calls=20):
+    """GB/s of the library's streaming copy kernel on `mbytes` MB (read + write)."""
+    import torch
+    n = mbytes * (1 << 20)
+    a = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    lbm.copy_probe(a, b)
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(calls):
+        lbm.copy_probe(a, b)
+    end.record()
+    torch.cuda.synchronize()
+    sec = start.elapsed_time(end) / 1e3 / calls
+    return {"kernel": "k_copy16", "bytes_per_call": 2 * n, "GBps": round(2 * n / sec / 1e9, 1),
+            "frac_of_peak": round(2 * n / sec / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def precision_errors(storage):
     """Relative errors of the coexistence densities, Laplace jump and D^2
     slope of a run with this storage against the FP64 oracle's values
-    (stored in tests/golden/precision_refs.json by the oracle)."""
+    (stored in tests/golden/precision_refs.json by the oracle), with each
+    case's grid and window."""
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import precision_metrics as PM
     from paper_2201_06039_amd import lbm, workloads as W
@@ -137,8 +196,60 @@ def precision_errors(storage):
 
     out = {}
     for case in PM.CASES:
-        for k, v in PM.relative_errors(case, PM.run_case(case, make), refs[case]).items():
-            out[f"{case}_{k}"] = float(f"{v:.3e}")
+        errs = {k: float(f"{v:.3e}") for k, v in PM.relative_errors(case, PM.run_case(case, make), refs[case]).items()}
+        out[case] = {"case": PM.describe(case), "relative_errors": errs,
+                     "within_bound": max(errs.values()) <= PRECISION_BOUND}
+    return out
+
+
+def d2_full_size(lbm, W, storages, steps=60000, every=1000):
+    """The D^2 test at the size the paper states (Sec. IV A: 100^3, D_0 = 50):
+    (D/D_0)^2 read out every `every` steps, and the relative error of its
+    slope in each window against the FP64 oracle's run
+    (tests/golden/d2_full_oracle.json, windows it reached) -- or, where the
+    oracle's run does not reach a window, against the FP64 kernel, which
+    matches the oracle to 1e-12 per step (the reference is named per window)."""
+    import numpy as np
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import precision_metrics as PM
+    w = W.load("d2_law_100")
+    fields = W.fields(w)
+    times = np.arange(every, steps + 1, every)
+    ref_path = os.path.join(ROOT, "tests", "golden", "d2_full_oracle.json")
+    oracle = None
+    if os.path.exists(ref_path):
+        with open(ref_path) as fh:
+            ref = json.load(fh)
+        if ref.get("every") == every and ref["times"] == [int(t) for t in times[:len(ref["times"])]]:
+            oracle = np.array(ref["d2"])
+    windows = [(w0, w1) for w0, w1 in ((5000, 10000), (10000, 20000), (20000, 40000), (40000, 60000)) if w1 <= steps]
+    need_f64 = oracle is None or len(oracle) < len(times)
+    runs = list(storages) + (["f64"] if need_f64 and "f64" not in storages else [])
+    curves = {}
+    for storage in runs:
+        lat = lbm.Lattice(w["params"], storage=storage, device="cuda:0", stream=new_stream())
+        lat.init_fields(*fields)
+        d2 = []
+        for _ in times:
+            lat.step(every)
+            d2.append(PM.d2_ratio(lat.rho_u_T()[0], w))
+        lat.close()
+        curves[storage] = np.array(d2)
+        print(f"# d2 100^3 {storage}: d2(end) = {d2[-1]:.5f}", file=sys.stderr, flush=True)
+    out = {"workload": "d2_law_100", "grid": [100, 100, 100], "D0": 50, "steps": steps, "every": every,
+           "windows": {}, "d2_end": {k: round(float(c[-1]), 6) for k, c in curves.items()}}
+    for w0, w1 in windows:
+        sel = (times >= w0) & (times <= w1)
+        idx = np.nonzero(sel)[0]
+        if oracle is not None and len(oracle) > idx[-1]:
+            base, ref_curve = "FP64 oracle", oracle[idx]
+        else:
+            base, ref_curve = "FP64 kernel", curves["f64"][sel]
+        ref_slope = np.polyfit(times[sel], ref_curve, 1)[0]
+        errs = {name: round(float((np.polyfit(times[sel], c[sel], 1)[0] - ref_slope) / abs(ref_slope)), 5)
+                for name, c in curves.items() if name in storages}
+        out["windows"][f"{w0}-{w1}"] = {"reference": base, "slope_relative_error": errs,
+                                       "within_bound": {k: abs(v) <= PRECISION_BOUND for k, v in errs.items()}}
     return out
 
 
@@ -150,7 +261,7 @@ def batch_run(storage, steps, warmup, name="batch_256", launch=None):
     from paper_2201_06039_amd import lbm, workloads as W
     wb = W.load(name)
     cases = wb["cases"]
-    b = lbm.Batch([c["params"] for c in cases], storage=storage, device="cuda:0")
+    b = lbm.Batch([c["params"] for c in cases], storage=storage, device="cuda:0", stream=new_stream())
     for i, c in enumerate(cases):
         b.init_case(i, *W.fields(c))
     if launch:
@@ -174,15 +285,24 @@ def batch_run(storage, steps, warmup, name="batch_256", launch=None):
     slots = sum(-(-c["params"]["nx"] // tx) * tx * -(-c["params"]["ny"] // ty) * ty * c["params"]["nz"] for c in cases)
     return {"workload": name, "cases": len(cases), "nodes": nodes, "storage": storage,
             "value": round(nodes / ms / 1e3, 2), "unit": "MLUPS", "ms_per_step": round(ms, 5), "steps": steps,
-            "roofline_frac": round(BYTES_PER_LUP[storage] * nodes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-            "launch": launch, "autotune_ms_per_step": tuned_ms,
+            "roofline_frac": round(bytes_alg(storage) * nodes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "bytes_per_lup": bytes_alg(storage), "launch": launch, "autotune_ms_per_step": tuned_ms,
             "thread_slot_efficiency": round(nodes / slots, 4), "graph": True}
+
+
+def rate_row(nn, ms, steps, storage, launch, launches, q19t=False):
+    sec = ms / 1e3 / steps
+    return {"MLUPS": round(nn / sec / 1e6, 2), "ms_per_step": round(ms / steps, 5),
+            "roofline_frac": round(bytes_alg(storage, q19t) * nn / sec / 1e9 / HBM_PEAK_GBS, 4),
+            "bytes_per_lup": bytes_alg(storage, q19t), "launches_per_step": launches,
+            "tile": [launch["tile_x"], launch["tile_y"]], "chunk_z": launch["chunk_z"]}
 
 
 def other_workloads(lbm, W, names, steps, warmup, storages=("f16", "f32")):
     """MLUPS and roofline fraction of the step on further workloads (the
-    pool-boiling wall grid by default; its step adds the rho_ave reduction
-    launch, which the fraction counts)."""
+    pool-boiling wall grid adds the rho_ave reduction launch, which the
+    fraction counts, and the 128^3 evaporation grid fits the 256 MB
+    Infinity Cache in FP16)."""
     out = {}
     for name in names:
         w = W.load(name)
@@ -191,58 +311,10 @@ def other_workloads(lbm, W, names, steps, warmup, storages=("f16", "f32")):
         nn = p["nx"] * p["ny"] * p["nz"]
         row = {"grid": [p["nx"], p["ny"], p["nz"]]}
         for storage in storages:
-            ms, launch, launches = timed_run(lbm, p, fields, storage, steps, warmup)
-            sec = ms / 1e3 / steps
-            row[storage] = {"MLUPS": round(nn / sec / 1e6, 2), "ms_per_step": round(ms / steps, 5),
-                            "roofline_frac": round(bytes_per_lup(storage) * nn / sec / 1e9 / HBM_PEAK_GBS, 4),
-                            "launches_per_step": launches, "tile": [launch["tile_x"], launch["tile_y"]],
-                            "chunk_z": launch["chunk_z"]}
+            ms, launch, launches, _ = timed_run(lbm, p, fields, storage, steps, warmup)
+            row[storage] = rate_row(nn, ms, steps, storage, launch, launches)
             print(f"# {name} {storage}: {ms / steps:.5f} ms/step", file=sys.stderr, flush=True)
         out[name] = row
-    return out
-
-
-def d2_full(lbm, W, storages=("f64", "f32", "f32dev", "f16", "bf16"), steps=60000, every=1000):
-    """The D^2 test at the size the paper states (Sec. IV A: 100^3, D_0 = 50)
-    for `steps` steps in every storage format: (D/D_0)^2 read out every
-    `every` steps, and the slope of each window against that of the FP64
-    kernel (and of the FP64 oracle, where tests/golden/d2_full_oracle.json
-    holds its values)."""
-    import numpy as np
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
-    import precision_metrics as PM
-    w = W.load("d2_law_100")
-    fields = W.fields(w)
-    times = np.arange(every, steps + 1, every)
-    curves = {}
-    for storage in storages:
-        lat = lbm.Lattice(w["params"], storage=storage, device="cuda:0")
-        lat.init_fields(*fields)
-        d2 = []
-        for _ in times:
-            lat.step(every)
-            d2.append(PM.d2_ratio(lat.rho_u_T()[0], w))
-        lat.close()
-        curves[storage] = np.array(d2)
-        print(f"# d2_full {storage}: d2(end) = {d2[-1]:.5f}", file=sys.stderr, flush=True)
-    ref_path = os.path.join(ROOT, "tests", "golden", "d2_full_oracle.json")
-    if os.path.exists(ref_path):
-        with open(ref_path) as fh:
-            ref = json.load(fh)
-        if ref["times"] == [int(t) for t in times]:
-            curves["oracle"] = np.array(ref["d2"])
-    windows = [(w0, w1) for w0, w1 in ((5000, 10000), (10000, 20000), (20000, 40000), (40000, 60000)) if w1 <= steps]
-    out = {"workload": "d2_law_100", "steps": steps, "every": every, "slope_relative_error": {}, "d2_end": {}}
-    for name, c in curves.items():
-        out["d2_end"][name] = round(float(c[-1]), 6)
-    base = "oracle" if "oracle" in curves else "f64"
-    out["reference"] = base
-    for w0, w1 in windows:
-        sel = (times >= w0) & (times <= w1)
-        ref_slope = np.polyfit(times[sel], curves[base][sel], 1)[0]
-        out["slope_relative_error"][f"{w0}-{w1}"] = {
-            name: round(float((np.polyfit(times[sel], c[sel], 1)[0] - ref_slope) / abs(ref_slope)), 5)
-            for name, c in curves.items() if name != base}
     return out
 
 
@@ -256,10 +328,8 @@ def lattice_comparison(lbm, p, fields, steps, warmup, storages=("f16", "f32")):
     for storage in storages:
         row = {}
         for name, extra in (("d3q7", dict(thermal_bgk=1)), ("d3q19", dict(thermal_bgk=1, thermal_lattice=1))):
-            ms, launch, _ = timed_run(lbm, dict(p, **extra), fields, storage, steps, warmup)
-            row[name] = {"MLUPS": round(nn * steps / (ms / 1e3) / 1e6, 2), "ms_per_step": round(ms / steps, 5),
-                         "bytes_per_lup": bytes_per_lup(storage, name == "d3q19"),
-                         "tile": [launch["tile_x"], launch["tile_y"]], "chunk_z": launch["chunk_z"]}
+            ms, launch, launches, _ = timed_run(lbm, dict(p, **extra), fields, storage, steps, warmup)
+            row[name] = rate_row(nn, ms, steps, storage, launch, launches, q19t=name == "d3q19")
             print(f"# temperature lattice {name} {storage}: {ms / steps:.5f} ms/step", file=sys.stderr, flush=True)
         row["speedup_of_d3q7"] = round(row["d3q19"]["ms_per_step"] / row["d3q7"]["ms_per_step"], 3)
         row["bytes_ratio"] = round(row["d3q19"]["bytes_per_lup"] / row["d3q7"]["bytes_per_lup"], 3)
@@ -270,17 +340,15 @@ def lattice_comparison(lbm, p, fields, steps, warmup, storages=("f16", "f32")):
 def divergence_comparison(lbm, p, fields, steps, warmup, storages=("f16", "f32")):
     """The step with div u of Eq. (48) at every node against the practice it
     replaces, isotropic finite differences of u(t) at interior nodes, which
-    needs u at every node before the step (here two more passes over the
-    state, into FP64 staging planes)."""
+    needs u at every node before the step (a velocity pass of the step's
+    shape first)."""
     nn = p["nx"] * p["ny"] * p["nz"]
     out = {}
     for storage in storages:
         row = {}
         for name, mode in (("local_eq48", 0), ("finite_difference", 1)):
-            ms, launch, launches = timed_run(lbm, dict(p, divu_mode=mode), fields, storage, steps, warmup)
-            row[name] = {"MLUPS": round(nn * steps / (ms / 1e3) / 1e6, 2), "ms_per_step": round(ms / steps, 5),
-                         "launches_per_step": launches, "tile": [launch["tile_x"], launch["tile_y"]],
-                         "chunk_z": launch["chunk_z"]}
+            ms, launch, launches, _ = timed_run(lbm, dict(p, divu_mode=mode), fields, storage, steps, warmup)
+            row[name] = rate_row(nn, ms, steps, storage, launch, launches)
             print(f"# divergence {name} {storage}: {ms / steps:.5f} ms/step", file=sys.stderr, flush=True)
         row["speedup_of_local"] = round(row["finite_difference"]["ms_per_step"] / row["local_eq48"]["ms_per_step"], 3)
         out[storage] = row
@@ -290,17 +358,18 @@ def divergence_comparison(lbm, p, fields, steps, warmup, storages=("f16", "f32")
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="evaporation_128")
-    ap.add_argument("--storage", default="f16", choices=sorted(BYTES_PER_LUP))
-    ap.add_argument("--compare", default="f32", choices=sorted(BYTES_PER_LUP) + ["none"],
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="multi_droplet_512")
+    ap.add_argument("--storage", default="f16", choices=sorted(BYTES_ALG))
+    ap.add_argument("--compare", default="f32", choices=sorted(BYTES_ALG) + ["none"],
                     help="second storage format timed on the same workload")
     ap.add_argument("--thermal-lattice", default="d3q7", choices=["d3q7", "d3q19"],
                     help="temperature lattice of the timed step (d3q19 runs the BGK collision)")
     ap.add_argument("--tile", default=None, help="TXxTY, e.g. 64x4")
     ap.add_argument("--chunk", type=int, default=None)
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-d2-full-size", action="store_true", help="skip the 100^3 D^2 windows in the precision leg")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-only", action="store_true", help="run only the batched leg and print its JSON")
     ap.add_argument("--batch-steps", type=int, default=200)
@@ -309,16 +378,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lattice-comparison", action="store_true")
     ap.add_argument("--no-workloads", action="store_true", help="skip the other-workload leg")
+    ap.add_argument("--no-copy", action="store_true", help="skip the streaming-copy ceiling")
     ap.add_argument("--d2-full", action="store_true",
                     help="only run the D^2 test at 100^3 for 60000 steps in every storage format (about 40 s) "
                          "and print its JSON")
-    ap.add_argument("--workloads", default="pool_boiling_256x256x384",
+    ap.add_argument("--workloads", default="evaporation_128,pool_boiling_256x256x384",
                     help="comma-separated workloads timed in the other-workload leg")
     ap.add_argument("--divu", default="local", choices=["local", "fd"],
                     help="velocity divergence of the timed step: Eq. (48) or finite differences")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
-                    help="only run 20 plain device-to-device copies of MB megabytes (to calibrate the "
-                         "FETCH_SIZE/WRITE_SIZE counters against a kernel of known traffic) and exit")
+                    help="only run 21 streaming copies of MB megabytes with the library's copy kernel (to "
+                         "calibrate the FETCH_SIZE/WRITE_SIZE counters against a kernel of known traffic) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -327,28 +397,14 @@ def main():
         sys.exit(2)
 
     import torch
-
-    if args.copy_probe:
-        n = args.copy_probe * (1 << 20) // 4
-        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        start.record()
-        for _ in range(20):
-            b.copy_(a)
-        end.record()
-        torch.cuda.synchronize()
-        sec = start.elapsed_time(end) / 1e3 / 20
-        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "calls": 21,
-                          "copy_probe_GBps": round(8 * n / sec / 1e9, 1)}))
-        return
-
     from paper_2201_06039_amd import lbm, workloads as W
 
+    if args.copy_probe:
+        print(json.dumps(dict(copy_ceiling(lbm, args.copy_probe), calls=21)), flush=True)
+        return
+
     if args.d2_full:
-        print(json.dumps(d2_full(lbm, W)), flush=True)
+        print(json.dumps(d2_full_size(lbm, W, ("f64", "f32", "f32dev", "f16", "bf16"))), flush=True)
         return
 
     if args.batch_only:
@@ -358,29 +414,37 @@ def main():
         return
 
     w = W.load(args.workload)
+    t0 = time.perf_counter()
     fields = W.fields(w)
+    print(f"# fields of {args.workload}: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     p = dict(w["params"])
     q19t = args.thermal_lattice == "d3q19"
     if q19t:
-        if args.storage not in BYTES_PER_LUP_Q19T:
-            ap.error(f"the D3Q19 temperature lattice is built for {sorted(BYTES_PER_LUP_Q19T)}")
+        if args.storage not in BYTES_ALG_Q19T:
+            ap.error(f"the D3Q19 temperature lattice is built for {sorted(BYTES_ALG_Q19T)}")
         p.update(thermal_lattice=1, thermal_bgk=1)
     fd = args.divu == "fd"
     if fd:
         p["divu_mode"] = 1
     nn = p["nx"] * p["ny"] * p["nz"]
+    extras = not q19t and not fd
 
     print(f"# workload {args.workload} {p['nx']}x{p['ny']}x{p['nz']} storage {args.storage}", file=sys.stderr,
           flush=True)
-    ms, launch, launches = timed_run(lbm, p, fields, args.storage, args.steps, args.warmup, args.tile, args.chunk)
-    print(f"# {args.storage}: {ms / args.steps:.5f} ms/step, launch {launch}", file=sys.stderr, flush=True)
+    ms, launch, launches, reps = timed_run(lbm, p, fields, args.storage, args.steps, args.warmup, args.tile,
+                                           args.chunk, repeats=5)
+    print(f"# {args.storage}: {ms / args.steps:.5f} ms/step, launch {launch}, repeats {reps}", file=sys.stderr,
+          flush=True)
 
     sec = ms / 1e3
     mlups = nn * args.steps / sec / 1e6
-    avg_launch_s = sec / args.steps  # the step kernel is the only launch per step when launches == 1
-    bytes_alg = bytes_per_lup(args.storage, q19t) * nn
-    achieved = bytes_alg / avg_launch_s / 1e9
+    # One launch per step here (periodic grid, no gravity, Eq. (48)): the
+    # average step time is the step kernel's average launch duration.
+    avg_launch_s = sec / args.steps / launches
+    balg = bytes_alg(args.storage, q19t) * nn
+    achieved = balg / avg_launch_s / 1e9
     arith = "f64" if args.storage == "f64" else "f32"
+    med = statistics.median(reps) / args.steps
     out = {
         "metric": METRIC,
         "value": round(mlups, 2),
@@ -398,39 +462,54 @@ def main():
                    "temperature_lattice": args.thermal_lattice.upper() + (" BGK" if q19t else " MRT"),
                    "velocity_divergence": "finite differences" if fd else "Eq. (48)",
                    "tile": [launch["tile_x"], launch["tile_y"]], "chunk_z": launch["chunk_z"],
-                   "workgroups": launch["workgroups"], "launches_per_step": launches},
+                   "workgroups": launch["workgroups"], "launches_per_step": launches,
+                   "timing": "HIP events on the library's stream, pairs of steps as graph replays"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(args.workload, args.storage, launch, q19t),
-                     "kernel": "k_step", "bytes_per_lup": bytes_per_lup(args.storage, q19t)},
+                     "kernel": "k_step", "bytes_per_lup": bytes_alg(args.storage, q19t),
+                     "frac_with_references": None if q19t else round(
+                         BYTES_WITH_REFERENCES[args.storage] * nn / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4),
+                     "bytes_per_lup_with_references": None if q19t else BYTES_WITH_REFERENCES[args.storage]},
+        "repeats": {"runs": len(reps), "ms_per_step": [round(r / args.steps, 5) for r in reps],
+                    "median_ms_per_step": round(med, 5), "median_MLUPS": round(nn / (med / 1e3) / 1e6, 2)},
     }
-    if args.compare != "none" and args.compare != args.storage and (not q19t or args.compare in BYTES_PER_LUP_Q19T):
-        ms2, launch2, _ = timed_run(lbm, p, fields, args.compare, args.steps, args.warmup)
+    if args.compare != "none" and args.compare != args.storage and (not q19t or args.compare in BYTES_ALG_Q19T):
+        ms2, launch2, launches2, _ = timed_run(lbm, p, fields, args.compare, args.steps, args.warmup)
         print(f"# {args.compare}: {ms2 / args.steps:.5f} ms/step, launch {launch2}", file=sys.stderr, flush=True)
-        sec2 = ms2 / 1e3 / args.steps
-        out["compare"] = {"storage": args.compare, "value": round(nn / sec2 / 1e6, 2), "unit": "MLUPS",
-                          "ms_per_step": round(ms2 / args.steps, 5),
-                          "roofline_frac": round(bytes_per_lup(args.compare, q19t) * nn / sec2 / 1e9 / HBM_PEAK_GBS, 4),
-                          "bytes_per_lup": bytes_per_lup(args.compare, q19t),
-                          "tile": [launch2["tile_x"], launch2["tile_y"]], "chunk_z": launch2["chunk_z"],
-                          "speedup_of_storage": round(ms2 / ms, 3)}
-    if not args.no_lattice_comparison and not q19t and not fd:
-        out["temperature_lattice_comparison"] = lattice_comparison(lbm, p, fields, max(1, args.steps // 2),
-                                                                   args.warmup)
-        out["divergence_comparison"] = divergence_comparison(lbm, p, fields, max(1, args.steps // 4), args.warmup)
-    if not args.no_workloads and not q19t and not fd and args.workloads:
+        row = rate_row(nn, ms2, args.steps, args.compare, launch2, launches2, q19t)
+        row.update(storage=args.compare, value=row["MLUPS"], unit="MLUPS", speedup_of_storage=round(ms2 / ms, 3))
+        out["compare"] = row
+    if not args.no_copy:
+        out["copy_ceiling"] = copy_ceiling(lbm)
+        print(f"# copy ceiling: {out['copy_ceiling']}", file=sys.stderr, flush=True)
+    del fields
+    if not args.no_workloads and extras and args.workloads:
         out["workloads"] = other_workloads(lbm, W, args.workloads.split(","), 200, 10)
-    if not args.no_precision and not q19t and not fd:
+    if not args.no_lattice_comparison and extras:
+        w128 = W.load("evaporation_128")
+        f128 = W.fields(w128)
+        out["temperature_lattice_comparison"] = dict(
+            workload="evaporation_128", **lattice_comparison(lbm, w128["params"], f128, 500, 20))
+        out["divergence_comparison"] = dict(
+            workload="evaporation_128", **divergence_comparison(lbm, w128["params"], f128, 250, 20))
+    if not args.no_precision and extras:
         errs = precision_errors(args.storage)
         print(f"# precision of {args.storage}: {errs}", file=sys.stderr, flush=True)
-        out["precision"] = {"storage": args.storage, "reference": "FP64 oracle", "bound": PRECISION_BOUND,
-                            "relative_errors": errs, "within_bound": max(errs.values()) <= PRECISION_BOUND}
-    if not args.no_batch and not q19t and not fd:
+        prec = {"storage": args.storage, "reference": "FP64 oracle", "bound": PRECISION_BOUND, "cases": errs}
+        if not args.no_d2_full_size:
+            prec["d2_100"] = d2_full_size(lbm, W, (args.storage,))
+        flags = [c["within_bound"] for c in errs.values()]
+        if "d2_100" in prec:
+            flags += [v[args.storage] for win in prec["d2_100"]["windows"].values() for v in [win["within_bound"]]]
+        prec["within_bound"] = all(flags)
+        out["precision"] = prec
+    if not args.no_batch and extras:
         bl = tuple(int(v) for v in args.batch_launch.split("x")) if args.batch_launch else None
         out["batch"] = batch_run(args.storage if args.storage != "f64" else "f32", args.batch_steps, 10, launch=bl)
         print(f"# batch: {out['batch']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, fields)
+        out["cpu_baseline"] = cpu_baseline(w, W.fields(w))
     print(json.dumps(out), flush=True)
 
 

@@ -144,7 +144,10 @@ typedef struct lbm_handle lbm_handle;
  * the deviation formats, the rho_r and T_r planes), the phi_s history plane
  * (FP32, FP64 for F64 storage), six FP64 staging planes for init and readout,
  * block partial sums and a few scalars, each region 256-byte aligned.
- * 0 also when nx*ny*nz times the element size reaches 2^32 bytes. */
+ * 0 also when nx*ny*nz times the element size reaches 2^32 bytes, or one
+ * x-y plane of two elements a node does.  Grids whose population copy halves
+ * exceed 4 GiB are addressed with 64-bit plain pointers instead of buffer
+ * resources (same results). */
 size_t lbm_arena_bytes(const lbm_params *p);
 
 /* Validate p, derive the constants (T_c from a, b, R as in Sec. IV A; c_sT^2 =
@@ -162,7 +165,11 @@ int lbm_init_fields(lbm_handle *h, const double *rho, const double *ux, const do
 
 /* Enqueue n >= 0 fused time steps (Eq. (1)-(10) collide + stream of f,
  * Eq. (37)-(45), (48), (18), (23)-(24) of g) without blocking.  Step t uses the
- * mean density at t - 1 in F_b.  ESTATE before lbm_init_fields. */
+ * mean density at t - 1 in F_b.  ESTATE before lbm_init_fields.  On a
+ * non-NULL stream that is not being captured, pairs of steps are replays of
+ * a HIP graph of two steps, captured at the first use and kept until the
+ * launch shape changes; on the NULL stream, or while the caller captures the
+ * stream, the launches are enqueued directly. */
 int lbm_step(lbm_handle *h, int n);
 
 /* rho (Eq. (10)), u = (sum e f + F/2)/rho with the total force F (Eq. (10)),
@@ -265,6 +272,16 @@ int lbm_batch_autotune(lbm_batch *b, int steps, double *best_ms);
 
 /* Release host resources (graphs included); the arena stays with the caller. */
 void lbm_batch_destroy(lbm_batch *b);
+
+/* ---------------------------------------------------------------------------
+ * Measurement aid (not part of the model): copy `bytes` bytes (a multiple of
+ * 16; both pointers 16-byte aligned device memory, not overlapping) with a
+ * plain streaming kernel of 16-byte loads and stores, enqueued on the stream
+ * without blocking.  Its rate is the practical HBM ceiling the step kernels
+ * are compared with, and its known traffic calibrates the hardware counters.
+ * EINVAL on a bad argument.
+ * --------------------------------------------------------------------------- */
+int lbm_copy_probe(const void *src, void *dst, size_t bytes, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -25,6 +25,21 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Measurement build (ORC_FP32): the same source evaluated in single
+ * precision -- every double below, parameters and exported arguments
+ * included, becomes a float, and floating constants are single precision
+ * (gcc -fsingle-precision-constant).  It measures how far a plain FP32
+ * evaluation of the scheme drifts from the FP64 one; the FP64 build is the
+ * oracle. */
+#ifdef ORC_FP32
+#define double float
+#define sqrt sqrtf
+#define fabs fabsf
+#endif
 
 #define Q19 19
 #define Q7 7
@@ -808,3 +823,24 @@ void orc_forcing_moments(const orc_params *p, const double *F, const double *Fm,
 }
 
 double orc_rho_ave(const orc_sim *s) { return s->rho_ave; }
+
+/* Threads an OpenMP parallel region of the oracle uses (for reporting). */
+int orc_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Threads for the following parallel regions of the calling thread; n <= 0
+ * restores the number OpenMP started with. */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    static int initial = 0;
+    if (!initial) initial = omp_get_max_threads();
+    omp_set_num_threads(n > 0 ? n : initial);
+#else
+    (void)n;
+#endif
+}

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "lbm.h"
@@ -57,8 +58,11 @@ bool valid_params(const lbm_params *p) {
     if (!p) return false;
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return false;
     if (!valid_storage(p->storage)) return false;
-    // node byte offsets inside a plane must fit in 32 bits
+    // Node indices and element offsets are 32-bit: nx*ny*nz elements of a plane must span under 4 GiB.
+    // Byte offsets inside an x-y plane are 32-bit too (in the paired layout a node takes two elements).
     if ((size_t)p->nx * p->ny * p->nz * element_bytes(p->storage) >= (size_t)1 << 32) return false;
+    if ((size_t)p->nx * p->ny * 2 * (element_bytes(p->storage) > 4 ? element_bytes(p->storage) : 4) >= (size_t)1 << 32)
+        return false;
     if (p->bc_z != LBM_BC_PERIODIC && p->bc_z != LBM_BC_WALL_BOTTOM_OPEN_TOP) return false;
     if (p->bc_z == LBM_BC_WALL_BOTTOM_OPEN_TOP && p->nz < 3) return false;
     if (!(p->tau_e > 0.5) || !(p->tau_v > 0.5) || !(p->tau_q > 0.5) || !(p->tau_pi > 0.5)) return false;
@@ -251,6 +255,8 @@ struct lbm_handle {
     int initialized;
     int tile_x, tile_y, chunk_z;
     int workgroups;
+    int device;               // HIP device current at lbm_create (the arena's)
+    hipGraphExec_t exec[2];   // two steps starting from copy 0 / copy 1 (lbm_step on a stream)
     unsigned *status() { return (unsigned *)(r_scal + 8 * sizeof(double)); }
     double *rho_ave() { return (double *)r_scal; }
     double *mass() { return (double *)(r_scal + sizeof(double)); }
@@ -310,12 +316,22 @@ int workgroups_for(const lbm_handle *h, int tx, int ty, int cz) {
 }
 
 // The buffer-resource path addresses each half of a copy's planes (split at
-// plane 14) with 32-bit offsets.
-bool buffer_path(const Layout &L) {
+// plane 14; 20 with the D3Q19 temperature lattice) with 32-bit offsets.
+size_t split_low_bytes(const Layout &L) {
     const size_t split = L.qt == 19 ? lbm::PopLayout<19>::kSplit : lbm::PopLayout<7>::kSplit;
-    const size_t lo = split * L.stride * L.es;
+    return split * L.stride * L.es;
+}
+bool buffer_path(const Layout &L) {
+    const size_t lo = split_low_bytes(L);
     const size_t hi = copy_bytes(L) - lo;
     return lo <= 0xFFFFFFFFull && hi <= 0xFFFFFFFFull;
+}
+// Record counts of the two buffer resources of a copy (unused with plain pointers).
+void set_buffer_extents(const Layout &L, unsigned &lo, unsigned &hi) {
+    lo = hi = 0;
+    if (!buffer_path(L)) return;
+    lo = (unsigned)split_low_bytes(L);
+    hi = (unsigned)(copy_bytes(L) - split_low_bytes(L));
 }
 
 template <typename ST, int TX, int TY, bool WALLS>
@@ -393,6 +409,7 @@ int step_once(lbm_handle *h) {
     A.partials = h->partials();
     A.status = h->status();
     A.stride = h->L.stride;
+    set_buffer_extents(h->L, A.buf_lo_bytes, A.buf_hi_bytes);
     A.nx = h->p.nx;
     A.ny = h->p.ny;
     A.nz = h->p.nz;
@@ -417,6 +434,34 @@ int step_once(lbm_handle *h) {
     }
     h->cur = n;
     return LBM_OK;
+}
+
+// Captured graphs of two steps (from copy `from` back to it).  They hold the
+// launch shape, so lbm_set_launch drops them.
+void drop_step_graphs(lbm_handle *h) {
+    for (int k = 0; k < 2; ++k) {
+        if (h->exec[k]) (void)hipGraphExecDestroy(h->exec[k]);
+        h->exec[k] = nullptr;
+    }
+}
+
+int step_graph(lbm_handle *h, int from) {
+    if (h->exec[from]) return LBM_OK;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return LBM_EHIP;
+    int rc = LBM_OK;
+    for (int k = 0; k < 2 && !rc; ++k)
+        rc = with_format(h->p, [&](auto fmt) { return step_once<decltype(fmt)>(h); });
+    const hipError_t e = hipStreamEndCapture(h->stream, &g);
+    h->cur = from;  // capture launches nothing; the two steps end where they began
+    if (rc || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc ? rc : LBM_EHIP;
+    }
+    const hipError_t ei = hipGraphInstantiate(&h->exec[from], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) h->exec[from] = nullptr;
+    return hip_status(ei);
 }
 
 // Sum rho and T of the current state into mass/energy (and optionally rho_ave).
@@ -481,7 +526,8 @@ int lbm_create(const lbm_params *p, void *dev_arena, size_t arena_bytes, void *h
     h->initialized = 0;
     set_default_launch(h);
     h->workgroups = workgroups_for(h, h->tile_x, h->tile_y, h->chunk_z);
-    int rc = clear_status(h);
+    int rc = hip_status(hipGetDevice(&h->device));
+    if (!rc) rc = clear_status(h);
     if (rc) {
         free(h);
         return rc;
@@ -541,6 +587,19 @@ int lbm_init_fields(lbm_handle *h, const double *rho, const double *ux, const do
 int lbm_step(lbm_handle *h, int n) {
     if (!h || n < 0) return LBM_EINVAL;
     if (!h->initialized) return LBM_ESTATE;
+    if (h->stream && n >= 2) {
+        // Pairs of steps as graph replays, unless the caller is capturing
+        // this stream itself (then the launches go into the caller's graph).
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(h->stream, &cs) != hipSuccess) return LBM_EHIP;
+        if (cs == hipStreamCaptureStatusNone) {
+            for (; n >= 2; n -= 2) {
+                int rc = step_graph(h, h->cur);
+                if (!rc) rc = hip_status(hipGraphLaunch(h->exec[h->cur], h->stream));
+                if (rc) return rc;
+            }
+        }
+    }
     for (int k = 0; k < n; ++k) {
         const int rc = with_format(h->p, [&](auto fmt) { return step_once<decltype(fmt)>(h); });
         if (rc) return rc;
@@ -690,6 +749,7 @@ int lbm_set_launch(lbm_handle *h, int tile_x, int tile_y, int chunk_z) {
     h->tile_y = tile_y;
     h->chunk_z = cz;
     h->workgroups = nb;
+    drop_step_graphs(h);
     return LBM_OK;
 }
 
@@ -708,7 +768,11 @@ int lbm_launches_per_step(const lbm_handle *h) {
            (h->p.divu_mode == LBM_DIVU_FD ? 1 : 0);
 }
 
-void lbm_destroy(lbm_handle *h) { free(h); }
+void lbm_destroy(lbm_handle *h) {
+    if (!h) return;
+    drop_step_graphs(h);
+    free(h);
+}
 
 const char *lbm_strerror(int status) {
     switch (status) {
@@ -859,6 +923,7 @@ int build_batch_tables(lbm_batch *b) {
         A.partials = h->partials();
         A.status = h->status();
         A.stride = h->L.stride;
+        set_buffer_extents(h->L, A.buf_lo_bytes, A.buf_hi_bytes);
         A.ustage = nullptr;  // batches run the local divergence of Eq. (48)
         A.uout = nullptr;
         A.unn = 0;
@@ -1104,6 +1169,14 @@ int lbm_batch_autotune(lbm_batch *b, int steps, double *best_ms) {
     if (!b || steps < 1 || !best_ms) return LBM_EINVAL;
     for (int c = 0; c < b->n; ++c)
         if (!b->cases[c].initialized) return LBM_ESTATE;
+    // Status words as they stand (an instability flagged by earlier steps is
+    // reported after the sweep too; flags raised by the timed launches are not).
+    std::vector<unsigned> status(b->n, 0u);
+    for (int c = 0; c < b->n; ++c)
+        if (hipMemcpyAsync(&status[c], b->cases[c].status(), sizeof(unsigned), hipMemcpyDeviceToHost, b->stream) !=
+            hipSuccess)
+            return LBM_EHIP;
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return LBM_EHIP;
     // keep every phi_s plane: the timed launches update them in place
     size_t off = 0;
     for (int c = 0; c < b->n; ++c) {
@@ -1151,13 +1224,17 @@ int lbm_batch_autotune(lbm_batch *b, int steps, double *best_ms) {
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    // restore phi_s and the status words, install the fastest shape
+    // Restore phi_s and the status words whatever happened in the sweep (the
+    // first error is the one returned), and install the fastest shape.
     off = 0;
-    for (int c = 0; c < b->n && !rc; ++c) {
+    for (int c = 0; c < b->n; ++c) {
         const size_t bytes = b->cases[c].L.nn * b->cases[c].L.cs;
-        rc = hip_status(
+        int r = hip_status(
             hipMemcpyAsync(b->cases[c].phi(), b->d_phi_backup + off, bytes, hipMemcpyDeviceToDevice, b->stream));
-        if (!rc) rc = clear_status(b->cases + c);
+        if (!r)
+            r = hip_status(hipMemcpyAsync(b->cases[c].status(), &status[c], sizeof(unsigned), hipMemcpyHostToDevice,
+                                          b->stream));
+        if (!rc) rc = r;
         off += align_up(b->cases[c].L.stride * b->cases[c].L.cs, kAlign);
     }
     b->tile_x = bt[0];
@@ -1166,7 +1243,8 @@ int lbm_batch_autotune(lbm_batch *b, int steps, double *best_ms) {
     b->workgroups = bt[3];
     const int rc2 = batch_tables(b);
     if (!rc) rc = rc2;
-    if (!rc) rc = hip_status(hipStreamSynchronize(b->stream));
+    const int rc3 = hip_status(hipStreamSynchronize(b->stream));  // the status copies read `status`
+    if (!rc) rc = rc3;
     *best_ms = best;
     return rc;
 }
@@ -1180,3 +1258,33 @@ void lbm_batch_destroy(lbm_batch *b) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Measurement aid: a plain streaming copy (16-byte loads and stores, grid
+// stride), the practical HBM ceiling the step kernels are compared with.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+__global__ void __launch_bounds__(256) k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst, size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+}  // namespace
+
+extern "C" int lbm_copy_probe(const void *src, void *dst, size_t bytes, void *hip_stream) {
+    if (!src || !dst || bytes == 0 || bytes % 16 != 0 || ((uintptr_t)src | (uintptr_t)dst) % 16 != 0)
+        return LBM_EINVAL;
+    const size_t n = bytes / 16;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        return LBM_EHIP;
+    size_t blocks = (n + 255) / 256;
+    const size_t cap = (size_t)cus * 32;  // enough resident waves to saturate HBM, then grid stride
+    if (blocks > cap) blocks = cap;
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)hip_stream, (const uint4 *)src,
+                       (uint4 *)dst, n);
+    return hip_status(hipGetLastError());
+}

@@ -359,8 +359,8 @@ __device__ __forceinline__ void buf_st(T x, __amdgpu_buffer_rsrc_t r, unsigned v
     }
 }
 
-constexpr int kBufferFlags = 0x00020000;  // raw dword buffer; the record count is left at its maximum and
-                                          // every offset is kept inside the planes by construction
+constexpr int kBufferFlags = 0x00020000;  // raw dword buffer; the record count of each resource is the byte
+                                          // size of the planes behind it
 
 // Access to the planes of the two ping-pong copies.
 //
@@ -461,13 +461,16 @@ struct PopIO<T, R, true, QT> {
     __amdgpu_buffer_rsrc_t in_lo, in_hi, out_lo, out_hi;
     unsigned sb;   // population plane stride in bytes (plain layout) or pair plane stride / 2
     unsigned rsb;  // reference plane stride in bytes
-    __device__ PopIO(const T *pin, T *pout, size_t stride) {
+    // lo_bytes, hi_bytes: the byte sizes of the planes below and above the
+    // split (each under 4 GiB on this path).
+    __device__ PopIO(const T *pin, T *pout, size_t stride, unsigned lo_bytes, unsigned hi_bytes) {
         sb = (unsigned)(stride * sizeof(T));
         rsb = (unsigned)(stride * sizeof(R));
-        in_lo = __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(pin), 0, -1, kBufferFlags);
-        in_hi = __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(pin) + kSplitPlane * stride, 0, -1, kBufferFlags);
-        out_lo = __builtin_amdgcn_make_buffer_rsrc(pout, 0, -1, kBufferFlags);
-        out_hi = __builtin_amdgcn_make_buffer_rsrc(pout + kSplitPlane * stride, 0, -1, kBufferFlags);
+        in_lo = __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(pin), 0, (int)lo_bytes, kBufferFlags);
+        in_hi = __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(pin) + kSplitPlane * stride, 0, (int)hi_bytes,
+                                                  kBufferFlags);
+        out_lo = __builtin_amdgcn_make_buffer_rsrc(pout, 0, (int)lo_bytes, kBufferFlags);
+        out_hi = __builtin_amdgcn_make_buffer_rsrc(pout + kSplitPlane * stride, 0, (int)hi_bytes, kBufferFlags);
     }
     // Whether population a sits behind the low resource, and the byte offset
     // of its plane from that resource's base (pair plane pair_of(a), 2 sb
@@ -513,6 +516,8 @@ struct PopIO<T, R, true, QT> {
     }
 };
 
+// Plain global pointers: the z offset `s` is a 64-bit byte count, since a
+// copy of a grid that needs this path spans more than 4 GiB.
 template <typename T, typename R, int QT>
 struct PopIO<T, R, false, QT> {
     using L = PopLayout<QT>;
@@ -521,28 +526,28 @@ struct PopIO<T, R, false, QT> {
     const T *in;
     T *out;
     size_t st;
-    __device__ PopIO(const T *pin, T *pout, size_t stride) : in(pin), out(pout), st(stride) {}
+    __device__ PopIO(const T *pin, T *pout, size_t stride, unsigned, unsigned) : in(pin), out(pout), st(stride) {}
     __device__ size_t plane_elems(int a) const {
         return PAIR ? (size_t)L::pair_of(a) * 2 * st + L::half_of(a) : a * st;
     }
-    __device__ T load(int a, unsigned v, unsigned s) const {
+    __device__ T load(int a, unsigned v, size_t s) const {
         return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(in + plane_elems(a)) + s + v);
     }
-    __device__ PairWord<T> load_pair(int p, unsigned v, unsigned s) const {
+    __device__ PairWord<T> load_pair(int p, unsigned v, size_t s) const {
         return *reinterpret_cast<const PairWord<T> *>(reinterpret_cast<const char *>(in + (size_t)p * 2 * st) + s + v);
     }
-    __device__ void store(int a, unsigned v, unsigned s, T x) const {
+    __device__ void store(int a, unsigned v, size_t s, T x) const {
         *reinterpret_cast<T *>(reinterpret_cast<char *>(out + plane_elems(a)) + s + v) = x;
     }
-    __device__ void store_pair(int p, unsigned v, unsigned s, PairWord<T> w) const {
+    __device__ void store_pair(int p, unsigned v, size_t s, PairWord<T> w) const {
         *reinterpret_cast<PairWord<T> *>(reinterpret_cast<char *>(out + (size_t)p * 2 * st) + s + v) = w;
     }
-    __device__ R load_ref(int k, unsigned v, unsigned s) const {
+    __device__ R load_ref(int k, unsigned v, size_t s) const {
         if constexpr (PAIR && sizeof(R) == sizeof(T)) return __builtin_bit_cast(R, load(kPopPlanes + k, v, s));
         const R *base = reinterpret_cast<const R *>(in + kPopPlanes * st) + k * st;
         return *reinterpret_cast<const R *>(reinterpret_cast<const char *>(base) + s + v);
     }
-    __device__ void store_ref(int k, unsigned v, unsigned s, R x) const {
+    __device__ void store_ref(int k, unsigned v, size_t s, R x) const {
         if constexpr (PAIR && sizeof(R) == sizeof(T)) {
             store(kPopPlanes + k, v, s, __builtin_bit_cast(T, x));
         } else {
@@ -570,6 +575,8 @@ struct StepArgs {
     double *__restrict__ partials;  // per-workgroup sum of rho (when gravity is on)
     unsigned *__restrict__ status;
     size_t stride;                  // elements between population planes
+    unsigned buf_lo_bytes, buf_hi_bytes;  // bytes of a copy below and above the buffer-resource split
+                                          // (the record counts of the two resources; buffer path only)
     // u(t) of Eq. (10) at every node, component planes `unn` values apart
     // (finite-difference divergence only): written by the velocity pass
     // (uout), read by the step (ustage)
@@ -628,6 +635,9 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     using LY = PopLayout<QT>;
     constexpr bool PAIR = paired_layout<E>();
     constexpr unsigned NS = PAIR ? 2 * sizeof(E) : sizeof(E);  // bytes between neighbouring nodes of a plane
+    // Byte offset of a z plane: 32 bits on the buffer-resource path (the
+    // scalar offset of the instruction), 64 bits with plain pointers.
+    using ZOff = std::conditional_t<BUF, unsigned, size_t>;
     constexpr int G0 = 19;  // first temperature plane
     constexpr unsigned RSZ = sizeof(typename ST::R);
     // node stride of the reference planes: 16-bit references share a pair plane
@@ -658,7 +668,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     }
     const int nx = A.nx, ny = A.ny, nz = A.nz;
     const unsigned plane = (unsigned)nx * (unsigned)ny;
-    const PopIO<E, typename ST::R, BUF, QT> io(A.pop_in, A.pop_out, A.stride);
+    const PopIO<E, typename ST::R, BUF, QT> io(A.pop_in, A.pop_out, A.stride, A.buf_lo_bytes, A.buf_hi_bytes);
 
     const int itx = logical % A.ntx;
     const int rest = logical / A.ntx;
@@ -737,22 +747,22 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     auto load_node = [&](unsigned row, unsigned zoff, Node &n) {
         if constexpr (PAIR) {
 #pragma unroll
-            for (int p = 0; p < WORDS; ++p) n.w[p] = io.load_pair(p, row * NS, zoff * NS);
+            for (int p = 0; p < WORDS; ++p) n.w[p] = io.load_pair(p, row * NS, (ZOff)zoff * NS);
             if constexpr (DEV && !REF_IN_PAIR) {
-                n.br = ST::rdec(io.load_ref(0, row * RSZ, zoff * RSZ));
-                n.bt = ST::rdec(io.load_ref(1, row * RSZ, zoff * RSZ));
+                n.br = ST::rdec(io.load_ref(0, row * RSZ, (ZOff)zoff * RSZ));
+                n.bt = ST::rdec(io.load_ref(1, row * RSZ, (ZOff)zoff * RSZ));
             } else if constexpr (!DEV) {
                 n.br = C(0);
                 n.bt = C(0);
             }
         } else {
 #pragma unroll
-            for (int a = 0; a < 19; ++a) n.e[a] = ST::dec(io.load(a, row * NS, zoff * NS));
+            for (int a = 0; a < 19; ++a) n.e[a] = ST::dec(io.load(a, row * NS, (ZOff)zoff * NS));
 #pragma unroll
-            for (int a = 0; a < QT; ++a) n.r[a] = ST::dec(io.load(G0 + a, row * NS, zoff * NS));
+            for (int a = 0; a < QT; ++a) n.r[a] = ST::dec(io.load(G0 + a, row * NS, (ZOff)zoff * NS));
             if constexpr (DEV) {
-                n.br = ST::rdec(io.load_ref(0, row * RSZ, zoff * RSZ));
-                n.bt = ST::rdec(io.load_ref(1, row * RSZ, zoff * RSZ));
+                n.br = ST::rdec(io.load_ref(0, row * RSZ, (ZOff)zoff * RSZ));
+                n.bt = ST::rdec(io.load_ref(1, row * RSZ, (ZOff)zoff * RSZ));
             } else {
                 n.br = C(0);
                 n.bt = C(0);
@@ -1056,17 +1066,17 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
             if (z + 2 <= zend && has_halo) load_node(hrow, (unsigned)zmap(z + 2) * plane, nxh);
         }
         // ---- streaming (push), Eq. (4) and Eq. (40) ----
-        const unsigned PB = plane * NS;
-        const unsigned Zc = (unsigned)z * PB;
-        unsigned Zo[3];
+        const ZOff PB = (ZOff)plane * NS;
+        const ZOff Zc = (ZOff)z * PB;
+        ZOff Zo[3];
         if (WALLS) {
-            Zo[0] = z > 0 ? Zc - PB : 0u;
+            Zo[0] = z > 0 ? Zc - PB : ZOff(0);
             Zo[1] = Zc;
-            Zo[2] = z < nz - 1 ? Zc + PB : 0u;
+            Zo[2] = z < nz - 1 ? Zc + PB : ZOff(0);
         } else {
-            Zo[0] = (unsigned)(z == 0 ? nz - 1 : z - 1) * PB;
+            Zo[0] = (ZOff)(z == 0 ? nz - 1 : z - 1) * PB;
             Zo[1] = Zc;
-            Zo[2] = (unsigned)(z == nz - 1 ? 0 : z + 1) * PB;
+            Zo[2] = (ZOff)(z == nz - 1 ? 0 : z + 1) * PB;
         }
         const unsigned rowb = irow * NS;
         // Values stored for the D3Q19 population a bound for the node in ring
@@ -1153,8 +1163,8 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
                 io.store_pair(LY::pair_of(LY::kPop), rowb, Zc,
                               word(__builtin_bit_cast(E, ST::renc(rho)), __builtin_bit_cast(E, ST::renc(T))));
             } else if constexpr (DEV) {
-                io.store_ref(0, irow * RU, (unsigned)z * plane * RU, ST::renc(rho));
-                io.store_ref(1, irow * RU, (unsigned)z * plane * RU, ST::renc(T));
+                io.store_ref(0, irow * RU, (ZOff)z * plane * RU, ST::renc(rho));
+                io.store_ref(1, irow * RU, (ZOff)z * plane * RU, ST::renc(T));
             }
           }
         }
@@ -1201,8 +1211,8 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
                 }
             }
             if constexpr (DEV) {
-                io.store_ref(0, irow * RU, (unsigned)z * plane * RU, ST::renc(rho));
-                io.store_ref(1, irow * RU, (unsigned)z * plane * RU, ST::renc(T));
+                io.store_ref(0, irow * RU, (ZOff)z * plane * RU, ST::renc(rho));
+                io.store_ref(1, irow * RU, (ZOff)z * plane * RU, ST::renc(T));
             }
         }
         if (P.gravity) rho_sum += (double)rho;

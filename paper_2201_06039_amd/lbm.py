@@ -45,7 +45,7 @@ EXPORTS = ("lbm_arena_bytes", "lbm_create", "lbm_init_fields", "lbm_step", "lbm_
            "lbm_launches_per_step", "lbm_destroy", "lbm_strerror",
            "lbm_batch_arena_bytes", "lbm_batch_create", "lbm_batch_init_case", "lbm_batch_step",
            "lbm_batch_get_rho_u_T", "lbm_batch_reduce", "lbm_batch_set_launch", "lbm_batch_get_launch",
-           "lbm_batch_autotune", "lbm_batch_destroy")
+           "lbm_batch_autotune", "lbm_batch_destroy", "lbm_copy_probe")
 
 _lib = None
 
@@ -96,10 +96,12 @@ def load_library():
     L.lbm_batch_autotune.argtypes = [vp, ctypes.c_int, dp]
     L.lbm_batch_destroy.argtypes = [vp]
     L.lbm_batch_destroy.restype = None
+    L.lbm_copy_probe.argtypes = [vp, vp, ctypes.c_size_t, vp]
     for name in ("lbm_create", "lbm_init_fields", "lbm_step", "lbm_get_rho_u_T", "lbm_reduce", "lbm_get_state",
                  "lbm_set_state", "lbm_set_launch", "lbm_get_launch", "lbm_launches_per_step",
                  "lbm_batch_create", "lbm_batch_init_case", "lbm_batch_step", "lbm_batch_get_rho_u_T",
-                 "lbm_batch_reduce", "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_autotune"):
+                 "lbm_batch_reduce", "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_autotune",
+                 "lbm_copy_probe"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -157,7 +159,12 @@ def _dp(a):
 
 
 class Lattice:
-    """One simulation on one GPU.  Host arrays are float64 of shape (nz, ny, nx)."""
+    """One simulation on one GPU.  Host arrays are float64 of shape (nz, ny, nx).
+
+    Work goes to `stream` (torch's current stream by default).  On a stream of
+    its own (e.g. torch.cuda.Stream(), default priority) lbm_step replays
+    pairs of steps as a captured graph; on the default stream it launches
+    them directly."""
 
     def __init__(self, params: dict, storage="f32", device="cuda", stream=None):
         import torch
@@ -170,7 +177,11 @@ class Lattice:
         if nbytes == 0:
             raise LbmError("lbm_arena_bytes", EINVAL)
         self.arena = torch.empty(nbytes, dtype=torch.uint8, device=device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.arena.device)
+        current = torch.cuda.current_stream(self.arena.device)
+        self.stream = stream if stream is not None else current
+        if self.stream != current:
+            # the arena was allocated on torch's current stream; order the lattice's stream after it
+            self.stream.wait_stream(current)
         h = ctypes.c_void_p()
         rc = self.lib.lbm_create(ctypes.byref(self._p), ctypes.c_void_p(self.arena.data_ptr()), nbytes,
                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
@@ -180,6 +191,8 @@ class Lattice:
 
     def close(self):
         if getattr(self, "_h", None):
+            # the arena goes back to torch's allocator: let the lattice's stream finish with it first
+            self.stream.synchronize()
             self.lib.lbm_destroy(self._h)
             self._h = None
 
@@ -314,3 +327,17 @@ class Batch:
         self._check("lbm_batch_autotune", self.lib.lbm_batch_autotune(self._h, int(steps), ctypes.byref(ms)))
         return ms.value
 
+
+def copy_probe(src, dst, stream=None):
+    """Enqueue the library's streaming copy of torch tensor `src` into `dst`
+    (same byte size, a multiple of 16) on `stream` (torch's current stream by
+    default)."""
+    import torch
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("copy_probe: tensors of different byte size")
+    stream = stream if stream is not None else torch.cuda.current_stream(src.device)
+    rc = load_library().lbm_copy_probe(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nbytes,
+                                       ctypes.c_void_p(stream.cuda_stream))
+    if rc != OK:
+        raise LbmError("lbm_copy_probe", rc)

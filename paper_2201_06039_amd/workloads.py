@@ -114,13 +114,24 @@ def multi_droplet(n, count, rmin, rmax, rho_l, rho_g, T, width=2.0, gap=4.0, see
         if ok:
             centres.append(c)
             radii.append(r)
-    x, y, z = _coords(n, n, n)
-    rho = np.full(x.shape, rho_g)
+    rho = np.full((n, n, n), rho_g)
+    # A droplet's profile equals rho_g to the last bit once tanh(2 d / width)
+    # rounds to 1 (d >= 10 width), so each droplet is evaluated only inside
+    # the periodic box of half-side r + 10 width + 1 around its centre.
+    reach = 10.0 * width + 1.0
     for c, r in zip(centres, radii):
-        dx = np.abs(x - c[0]); dx = np.minimum(dx, n - dx)
-        dy = np.abs(y - c[1]); dy = np.minimum(dy, n - dy)
-        dz = np.abs(z - c[2]); dz = np.minimum(dz, n - dz)
-        rho = np.maximum(rho, tanh_blend(np.sqrt(dx * dx + dy * dy + dz * dz) - r, rho_l, rho_g, width))
+        ax = []
+        for k in range(3):
+            lo = int(np.floor(c[k] - r - reach))
+            idx = np.arange(lo, int(np.ceil(c[k] + r + reach)) + 1)
+            if idx.size >= n:
+                idx = np.arange(n)
+            d = np.abs(np.mod(idx, n) - c[k])
+            ax.append((np.mod(idx, n), np.minimum(d, n - d)))
+        (ix, dx), (iy, dy), (iz, dz) = ax
+        dist = np.sqrt(dx[None, None, :] ** 2 + dy[None, :, None] ** 2 + dz[:, None, None] ** 2) - r
+        box = np.ix_(iz, iy, ix)
+        rho[box] = np.maximum(rho[box], tanh_blend(dist, rho_l, rho_g, width))
     zero = np.zeros_like(rho)
     return rho, zero, zero.copy(), zero.copy(), np.full_like(rho, T)
 

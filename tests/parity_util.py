@@ -55,3 +55,37 @@ def errors(got, ref):
     e["u"] = float(du.max() / un.max())
     e["u_l2"] = float(np.sqrt((du ** 2).sum() / (un ** 2).sum()))
     return e
+
+
+def block_oracle(w, fields, nodes, steps, half=8):
+    """The oracle's rho, u, T after `steps` steps at individual nodes of a
+    periodic grid, each from its own (2 half)^3 block of the initial fields
+    cut around the node (periodic indices).  A step reaches two nodes out
+    (the streaming and the 18-neighbour stencils) and the readout velocity one
+    more, so the block centre is exact while 2 steps + 2 <= half (no gravity:
+    rho_ave does not enter).  `nodes` is a list of (z, y, x); returns five
+    arrays of len(nodes)."""
+    from oracle import sim
+    assert 2 * steps + 2 <= half, "block too small for the step count"
+    nz, ny, nx = fields[0].shape
+    p = dict(w["params"], nx=2 * half, ny=2 * half, nz=2 * half)
+    assert p.get("bc_z", 0) == 0 and not p.get("bc_T_shell", 0) and not any(p.get("grav", (0, 0, 0)))
+    out = np.empty((5, len(nodes)))
+    for k, (z, y, x) in enumerate(nodes):
+        iz = np.arange(z - half, z + half) % nz
+        iy = np.arange(y - half, y + half) % ny
+        ix = np.arange(x - half, x + half) % nx
+        blk = [f[np.ix_(iz, iy, ix)] for f in fields]
+        s = sim.Sim(**p)
+        s.init_fields(*blk)
+        s.step(steps)
+        r = s.rho_u_T()
+        s.close()
+        for c in range(5):
+            out[c, k] = r[c][half, half, half]
+    return out
+
+
+def sample_errors(got, ref):
+    """errors() restricted to sampled nodes: got and ref are (5, n) arrays."""
+    return errors(tuple(got), tuple(ref))

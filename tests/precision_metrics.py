@@ -25,6 +25,19 @@ CASES = {
 }
 
 
+def describe(name):
+    """Grid, size and measurement window of a case, for reports."""
+    c = CASES[name]
+    w = case_workload(name)
+    p = w["params"]
+    d = {"workload": c["workload"], "grid": [p["nx"], p["ny"], p["nz"]], "steps": c["steps"]}
+    if name == "laplace":
+        d["radius"] = w["init"]["radius"]
+    if name == "d2":
+        d.update(D0=2 * w["init"]["radius"], window=[c["t0"], c["steps"]], every=c["every"])
+    return d
+
+
 def case_workload(name):
     c = CASES[name]
     w = copy.deepcopy(W.load(c["workload"]))

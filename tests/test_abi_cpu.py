@@ -164,3 +164,24 @@ def test_divergence_mode_validation(lib):
         assert lbm.arena_bytes(dict(p, divu_mode=1), fmt) > 0, fmt
     for fmt in ("bf16", "f32dev"):
         assert lbm.arena_bytes(dict(p, divu_mode=1), fmt) == 0, fmt
+
+
+def test_large_grid_limits(lib):
+    """Grids beyond the 4 GiB reach of a buffer resource are valid (their
+    copies are addressed with 64-bit plain pointers): a 1024 x 1024 x 600
+    FP32 grid needs two copies of 13 pair planes of 8 bytes a node plus the
+    reference-free tail, far past 2^32 bytes.  The limits that remain: the
+    grid's elements of one plane kind must span under 2^32 bytes, and so must
+    an x-y plane of the paired layout."""
+    from paper_2201_06039_amd import lbm, workloads as W
+    p = dict(W.load("static_droplet_32")["params"])
+    n = 1024 * 1024 * 600
+    big = dict(p, nx=1024, ny=1024, nz=600)
+    b = lbm.arena_bytes(big, "f32")
+    stride = -(-n // 128) * 128
+    assert b >= 2 * 26 * 4 * stride + 4 * n + 6 * 8 * n
+    assert b < 2 * 26 * 4 * stride + 4 * n + 6 * 8 * n + (1 << 27)  # + per-workgroup partial sums
+    assert lbm.arena_bytes(dict(p, nx=1024, ny=1024, nz=1100), "f16") > 0   # 2^30 < n < 2^31 for 2-byte elements
+    assert lbm.arena_bytes(dict(p, nx=1024, ny=1024, nz=1024), "f32") == 0  # n * 4 bytes reaches 2^32
+    assert lbm.arena_bytes(dict(p, nx=1024, ny=1024, nz=2048), "f16") == 0  # n * 2 bytes reaches 2^32
+    assert lbm.arena_bytes(dict(p, nx=1 << 15, ny=1 << 14, nz=1), "f16") == 0  # one paired plane reaches 2^32

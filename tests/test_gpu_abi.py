@@ -177,3 +177,43 @@ def test_full_size_evaporation_fp16():
         e = errors(run_gpu(w, steps, "f16"), run_oracle(w, steps))
         print(f"  errors {e}", flush=True)
         assert e["rho"] <= 2.0 ** -11 and e["T"] <= 2.0 ** -11 and e["u_l2"] <= 20 * 2.0 ** -11, e
+
+
+@pytest.mark.parametrize("case", ["gravity", "fd", "periodic_f16"])
+def test_step_graph_replay_equals_direct_launches(case):
+    """lbm_step on a stream of its own replays pairs of steps as a captured
+    HIP graph; on the default stream it launches them directly.  Both must
+    give the same bits after every readout of a schedule that mixes odd and
+    even step counts, eager readouts between replays (the graphs are replayed
+    many times, from both population copies), a launch-shape change (which
+    drops the graphs) and a checkpoint restore."""
+    import torch
+    from paper_2201_06039_amd import lbm
+    if case == "gravity":  # two launches a step: the step and the rho_ave reduction
+        w, storage, launch2 = workload("pool_boiling_32x32x48"), "f32", (32, 8, 5)
+    elif case == "fd":     # two launches a step: the velocity pass and the step
+        w, storage, launch2 = workload("evaporation_128", nx=40, ny=36, nz=20, radius=7.0, divu_mode=1), "f16", (64, 4, 3)
+    else:
+        w, storage, launch2 = workload("evaporation_128", nx=40, ny=36, nz=20, radius=7.0), "f16", (32, 16, 7)
+    print(f"graph replay {case}", flush=True)
+    fields = W.fields(w)
+    lats = [lbm.Lattice(w["params"], storage=storage, device="cuda:0"),
+            lbm.Lattice(w["params"], storage=storage, device="cuda:0", stream=torch.cuda.Stream(device="cuda:0"))]
+    for lat in lats:
+        lat.init_fields(*fields)
+    for k, n in enumerate([1, 4, 3, 2, 6, 5, 2]):
+        if k == 3:
+            for lat in lats:
+                lat.set_launch(*launch2)
+        if k == 5:
+            blob = lats[0].get_state()
+            for lat in lats:
+                lat.set_state(blob)
+        outs = []
+        for lat in lats:
+            lat.step(n)
+            outs.append(lat.rho_u_T())
+        for a, b in zip(*outs):
+            assert np.array_equal(a, b), (case, k, n)
+    for lat in lats:
+        lat.close()
