@@ -45,6 +45,7 @@ extern "C" {
 #define LBM_EHIP (-3)      /* HIP runtime error                                */
 #define LBM_EUNSTABLE (-4) /* a step produced rho <= 0, psi^2 < 0 or NaN       */
 #define LBM_ESTATE (-5)    /* call out of order (e.g. step before init)        */
+#define LBM_ESCRATCH (-6)  /* grid too large for lbm_reduce_static's scratch   */
 
 /* Boundary in z (x and y are always periodic). */
 #define LBM_BC_PERIODIC 0
@@ -180,6 +181,18 @@ int lbm_get_rho_u_T(lbm_handle *h, double *rho, double *ux, double *uy, double *
 
 /* FP64 sums of rho and T over the grid.  Synchronises; may return EUNSTABLE. */
 int lbm_reduce(lbm_handle *h, double *mass, double *energy);
+
+/* For callers that cannot allocate device memory or touch the arena's
+ * scratch (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): lbm_reduce with its partial sums and results in a
+ * static device array of the library (16 MiB on each GPU it runs on, held
+ * until the process ends) instead of the arena.  Allocates nothing; same
+ * kernels, same summation order, same results as lbm_reduce.  Up to
+ * 268,434,432 nodes (2^20 - 4 blocks of 256): ESCRATCH beyond.  All handles
+ * on one GPU share the array: calls that overlap on one GPU (other threads,
+ * other streams) race.  Synchronises the handle's stream; may return
+ * EUNSTABLE; ESTATE before init. */
+int lbm_reduce_static(lbm_handle *h, double *mass, double *energy);
 
 /* Size of the raw checkpoint: header, the stored planes (f, g and, for the
  * deviation formats, rho_r and T_r, in the storage format), phi_s history,

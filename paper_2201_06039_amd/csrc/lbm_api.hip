@@ -243,6 +243,47 @@ int with_format(const lbm_params &p, Fn &&fn) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Static scratch of lbm_reduce_static, the allocation-free variant of
+// lbm_reduce: its per-block partial sums of rho and T ([kScratchResults, ...))
+// and its two results ([0] mass, [1] energy) live in this file-scope device
+// array instead of the handle's arena.  Each GPU the library runs on holds
+// its own copy until the process ends.  Host code never names `scratch` in a
+// launch or a copy (on the host that name is not a device address): the
+// address of each device's copy is looked up once, with that device current,
+// at the first lbm_create on it, and kept in scratch_ptr[device].  Every call
+// writes the entries it reads (nothing must start at zero); calls that
+// overlap on one GPU share the array and race.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchDoubles = (size_t)1 << 21;  // 16 MiB a device
+constexpr size_t kScratchResults = 8;                // results first, partial sums after them
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+double *scratch_ptr[kMaxDevices];
+
+// The address of `device`'s copy of the scratch array (the device is current).
+int scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return LBM_EHIP;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (scratch_ptr[device]) return LBM_OK;
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LBM_EHIP;
+    scratch_ptr[device] = (double *)ptr;
+    return LBM_OK;
+}
+
+double *scratch_of(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    return scratch_ptr[device];
+}
+
+}  // namespace
+
 struct lbm_handle {
     lbm_params p;
     Layout L;
@@ -527,6 +568,7 @@ int lbm_create(const lbm_params *p, void *dev_arena, size_t arena_bytes, void *h
     set_default_launch(h);
     h->workgroups = workgroups_for(h, h->tile_x, h->tile_y, h->chunk_z);
     int rc = hip_status(hipGetDevice(&h->device));
+    if (!rc) rc = scratch_setup(h->device);
     if (!rc) rc = clear_status(h);
     if (rc) {
         free(h);
@@ -647,6 +689,40 @@ int lbm_reduce(lbm_handle *h, double *mass, double *energy) {
     double me[2];
     if (hipMemcpyAsync(me, h->mass(), 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess)
         return LBM_EHIP;
+    unsigned s = 0;
+    rc = check_status(h, &s);
+    if (rc) return rc;
+    *mass = me[0];
+    *energy = me[1];
+    if (s & 1u) {
+        clear_status(h);
+        return LBM_EUNSTABLE;
+    }
+    return LBM_OK;
+}
+
+int lbm_reduce_static(lbm_handle *h, double *mass, double *energy) {
+    if (!h || !mass || !energy) return LBM_EINVAL;
+    const size_t nb = (h->L.nn + 255) / 256;
+    if (2 * nb > kScratchDoubles - kScratchResults) return LBM_ESCRATCH;
+    if (!h->initialized) return LBM_ESTATE;
+    double *sp = scratch_of(h->device);
+    if (!sp) return LBM_EHIP;
+    // The kernels and block order of lbm_reduce, with the static scratch in
+    // place of the arena's partial sums and scalars.
+    int rc = with_format(h->p, [&](auto fmt) {
+        using ST = decltype(fmt);
+        hipLaunchKernelGGL(lbm::k_sum<ST>, dim3((unsigned)nb), dim3(256), 0, h->stream,
+                           (const typename ST::T *)h->pop(h->cur), h->L.stride, h->L.nn, sp + kScratchResults);
+        hipLaunchKernelGGL(lbm::k_finish, dim3(1), dim3(256), 0, h->stream, (const double *)(sp + kScratchResults),
+                           (int)nb, 2, 0, 1.0, sp);
+        hipLaunchKernelGGL(lbm::k_finish, dim3(1), dim3(256), 0, h->stream, (const double *)(sp + kScratchResults),
+                           (int)nb, 2, 1, 1.0, sp + 1);
+        return hip_status(hipGetLastError());
+    });
+    if (rc) return rc;
+    double me[2];
+    if (hipMemcpyAsync(me, sp, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess) return LBM_EHIP;
     unsigned s = 0;
     rc = check_status(h, &s);
     if (rc) return rc;
@@ -782,6 +858,7 @@ const char *lbm_strerror(int status) {
     case LBM_EHIP: return "HIP runtime error";
     case LBM_EUNSTABLE: return "unstable state (rho <= 0, psi^2 < 0 or NaN)";
     case LBM_ESTATE: return "call out of order";
+    case LBM_ESCRATCH: return "grid larger than the static scratch of lbm_reduce_static";
     }
     return "unknown status";
 }

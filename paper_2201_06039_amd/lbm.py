@@ -13,7 +13,7 @@ import numpy as np
 
 from . import build as _build
 
-OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, ESTATE, ESCRATCH = 0, -1, -2, -3, -4, -5, -6
 BC_PERIODIC, BC_WALL_BOTTOM_OPEN_TOP = 0, 1
 KAPPA_CONST_LAMBDA, KAPPA_CONST_CHI = 0, 1
 STORE_F32, STORE_F64, STORE_F16, STORE_BF16, STORE_F32_DEV = 0, 1, 2, 3, 4
@@ -41,6 +41,7 @@ class LbmParams(ctypes.Structure):
 
 # Every entry point declared in include/lbm.h.
 EXPORTS = ("lbm_arena_bytes", "lbm_create", "lbm_init_fields", "lbm_step", "lbm_get_rho_u_T", "lbm_reduce",
+           "lbm_reduce_static",
            "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_set_launch", "lbm_get_launch",
            "lbm_launches_per_step", "lbm_destroy", "lbm_strerror",
            "lbm_batch_arena_bytes", "lbm_batch_create", "lbm_batch_init_case", "lbm_batch_step",
@@ -73,6 +74,7 @@ def load_library():
     L.lbm_step.argtypes = [vp, ctypes.c_int]
     L.lbm_get_rho_u_T.argtypes = [vp, dp, dp, dp, dp, dp]
     L.lbm_reduce.argtypes = [vp, dp, dp]
+    L.lbm_reduce_static.argtypes = [vp, dp, dp]
     L.lbm_state_bytes.argtypes = [vp]
     L.lbm_state_bytes.restype = ctypes.c_size_t
     L.lbm_get_state.argtypes = [vp, vp, ctypes.c_size_t]
@@ -97,7 +99,8 @@ def load_library():
     L.lbm_batch_destroy.argtypes = [vp]
     L.lbm_batch_destroy.restype = None
     L.lbm_copy_probe.argtypes = [vp, vp, ctypes.c_size_t, vp]
-    for name in ("lbm_create", "lbm_init_fields", "lbm_step", "lbm_get_rho_u_T", "lbm_reduce", "lbm_get_state",
+    for name in ("lbm_create", "lbm_init_fields", "lbm_step", "lbm_get_rho_u_T", "lbm_reduce", "lbm_reduce_static",
+                 "lbm_get_state",
                  "lbm_set_state", "lbm_set_launch", "lbm_get_launch", "lbm_launches_per_step",
                  "lbm_batch_create", "lbm_batch_init_case", "lbm_batch_step", "lbm_batch_get_rho_u_T",
                  "lbm_batch_reduce", "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_autotune",
@@ -221,6 +224,12 @@ class Lattice:
     def reduce(self):
         m, e = ctypes.c_double(), ctypes.c_double()
         self._check("lbm_reduce", self.lib.lbm_reduce(self._h, ctypes.byref(m), ctypes.byref(e)))
+        return m.value, e.value
+
+    def reduce_static(self):
+        """lbm_reduce through the library's static scratch (allocates nothing)."""
+        m, e = ctypes.c_double(), ctypes.c_double()
+        self._check("lbm_reduce_static", self.lib.lbm_reduce_static(self._h, ctypes.byref(m), ctypes.byref(e)))
         return m.value, e.value
 
     def state_bytes(self):
