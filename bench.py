@@ -253,6 +253,67 @@ def d2_full_size(lbm, W, storages, steps=60000, every=1000):
     return out
 
 
+def bubble_departure(lbm, W, name, g=None, storage="f32", max_steps=30000, every=100):
+    """Sec. IV C: run the closed-box nucleation workload until a vapour bubble
+    leaves the hydrophobic square.  Every `every` steps the vapour nodes
+    (rho below the mid-density of the saturated phases) are split into
+    connected components; the first component that touches neither the wall
+    (z = 0) nor the vapour above the pool is the departed bubble, and its
+    equivalent-sphere diameter (6 V / pi)^(1/3) is D_d."""
+    import numpy as np
+    from scipy import ndimage
+    w = W.load(name)
+    p = dict(w["params"])
+    if g is not None:
+        p["grav"] = [0.0, 0.0, -g]
+    mid = 0.5 * (w["init"]["rho_l"] + w["init"]["rho_g"])
+    lat = lbm.Lattice(p, storage=storage, device="cuda:0", stream=new_stream())
+    lat.init_fields(*W.fields(w))
+    t0 = time.perf_counter()
+    out = {"workload": name, "g": -p["grav"][2], "storage": storage, "departure_step": None, "D_d": None,
+           "attached_max_D": 0.0, "readout_every": every}
+    t = 0
+    while t < max_steps:
+        lat.step(every)
+        t += every
+        rho = lat.rho_u_T()[0]
+        lab, n = ndimage.label(rho < mid)
+        if n == 0:
+            continue
+        ids = np.arange(1, n + 1)
+        vol = ndimage.sum_labels(np.ones_like(rho), lab, ids)
+        zmin = ndimage.minimum(np.broadcast_to(np.arange(p["nz"])[:, None, None], rho.shape), lab, ids)
+        zmax = ndimage.maximum(np.broadcast_to(np.arange(p["nz"])[:, None, None], rho.shape), lab, ids)
+        attached = [(v, i) for v, i, z0 in zip(vol, ids, zmin) if z0 == 0]
+        if attached:
+            out["attached_max_D"] = max(out["attached_max_D"], round(float((6 * max(attached)[0] / np.pi) ** (1 / 3)), 2))
+        free = [(v, i) for v, i, z0, z1 in zip(vol, ids, zmin, zmax) if z0 > 0 and z1 < p["nz"] - 1 and v > 1000]
+        if free:
+            v = max(free)[0]
+            out.update(departure_step=t, D_d=round(float((6 * v / np.pi) ** (1 / 3)), 2))
+            break
+    lat.close()
+    out["wall_s"] = round(time.perf_counter() - t0, 1)
+    print(f"# departure {name}: {out}", file=sys.stderr, flush=True)
+    return out
+
+
+def nucleation_study(lbm, W, name="nucleation_200x200x280", gravities=(1e-5, 1.5e-5, 2e-5, 3e-5, 4e-5)):
+    """Departure diameters over a range of gravities and the exponent of
+    D_d ~ g^n from a least-squares fit of log D_d against log g (the paper's
+    correlation line is D_d = 0.253 g^-0.5, Fig. 7)."""
+    import numpy as np
+    runs = [bubble_departure(lbm, W, name, g=g) for g in gravities]
+    ok = [r for r in runs if r["D_d"]]
+    for r in runs:
+        r["D_d_correlation"] = round(0.253 * r["g"] ** -0.5, 2)
+    out = {"runs": runs, "paper_correlation": "D_d = 0.253 g^-0.5"}
+    if len(ok) >= 2:
+        slope, icpt = np.polyfit(np.log([r["g"] for r in ok]), np.log([r["D_d"] for r in ok]), 1)
+        out.update(exponent=round(float(slope), 3), prefactor=round(float(np.exp(icpt)), 4))
+    return out
+
+
 def batch_run(storage, steps, warmup, name="batch_256", launch=None):
     """The batched step over the lattices of workload `name`: autotune the
     launch on the initial state (or take `launch` = (tile_x, tile_y, chunk_z,
@@ -382,6 +443,9 @@ def main():
     ap.add_argument("--d2-full", action="store_true",
                     help="only run the D^2 test at 100^3 for 60000 steps in every storage format (about 40 s) "
                          "and print its JSON")
+    ap.add_argument("--nucleation", action="store_true",
+                    help="only run the bubble nucleation and departure test of Sec. IV C at five gravities "
+                         "(about 3 minutes) and print its JSON")
     ap.add_argument("--workloads", default="evaporation_128,pool_boiling_256x256x384",
                     help="comma-separated workloads timed in the other-workload leg")
     ap.add_argument("--divu", default="local", choices=["local", "fd"],
@@ -405,6 +469,10 @@ def main():
 
     if args.d2_full:
         print(json.dumps(d2_full_size(lbm, W, ("f64", "f32", "f32dev", "f16", "bf16"))), flush=True)
+        return
+
+    if args.nucleation:
+        print(json.dumps(nucleation_study(lbm, W)), flush=True)
         return
 
     if args.batch_only:

@@ -53,6 +53,25 @@ extern "C" {
  * Dirichlet temperature (Eq. (51)); open top at z = nz-1 whose unknown f are
  * copied from the layer below and whose g obey Eq. (51) with T_top. */
 #define LBM_BC_WALL_BOTTOM_OPEN_TOP 1
+/* Closed box (Sec. IV C): halfway bounce-back walls below z = 0 and above
+ * z = nz-1 (Eq. (50)); anti-bounce-back Dirichlet temperature (Eq. (51)) at
+ * the bottom (T_wall, T_wall_patch) and at the top (T_top). */
+#define LBM_BC_WALLS 2
+
+/* Wettability of the bottom wall (walls only; the top wall and the open top
+ * see a copy of the top fluid layer).  NEUTRAL: a solid node below z = 0
+ * carries the density and temperature of the fluid node above it.
+ * VIRTUAL_DENSITY: the virtual-density scheme of Li, Luo, Kang & Chen
+ * (Phys. Rev. E 90, 053301, 2014) standing in for the paper's Ref. [52]: a
+ * solid node carries rho_w = phi rho_ave - drho, rho_ave the weighted mean of
+ * its five fluid neighbours (weights 1/18 and 1/36 of Eq. (5)), and psi of
+ * Eq. (8) at rho_w and the temperature of the fluid node above it; phi =
+ * wet_phi_in, drho = wet_drho inside a square of side wet_square centred at
+ * ((nx-1)/2, (ny-1)/2) (Sec. IV C's patterned wall), phi = wet_phi, drho = 0
+ * elsewhere.  phi > 1 wets (contact angle below 90 degrees), phi < 1 or
+ * drho > 0 does not.  Adds one launch per step. */
+#define LBM_WET_NEUTRAL 0
+#define LBM_WET_VIRTUAL_DENSITY 1
 
 /* Thermal conductivity mode of Eq. (17): chi = lambda/(rho c_V). */
 #define LBM_KAPPA_CONST_LAMBDA 0 /* kappa is lambda; chi varies with rho per node */
@@ -136,6 +155,11 @@ typedef struct lbm_params {
     int thermal_lattice;     /* LBM_THERMAL_*; D3Q19 stores 19 g planes        */
                              /* instead of 7 (38 population planes, not 26)   */
     int divu_mode;           /* LBM_DIVU_*                                     */
+    int wet_mode;            /* LBM_WET_* (walls only)                         */
+    double wet_phi;          /* > 0: phi outside the square                    */
+    double wet_phi_in;       /* > 0: phi inside the square                     */
+    double wet_drho;         /* >= 0: drho inside the square                   */
+    double wet_square;       /* >= 0: side of the centred square (0: none)     */
 } lbm_params;
 
 typedef struct lbm_handle lbm_handle;

@@ -49,7 +49,8 @@ enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_EUNSTABLE = -4 };
 /* Parameters of one simulation; field meaning follows the paper's symbols. */
 typedef struct orc_params {
     int nx, ny, nz;
-    int bc_z;              /* 0: periodic in z; 1: bounce-back wall below z=0, open top */
+    int bc_z;              /* 0: periodic in z; 1: bounce-back wall below z=0, open top;
+                              2: bounce-back walls below z=0 and above z=nz-1 (closed box) */
     double a, b, R;        /* Peng-Robinson constants, Eq. (49) */
     double acentric;       /* omega in Eq. (49) */
     double G;              /* interaction strength, Eq. (7)-(8) */
@@ -75,6 +76,13 @@ typedef struct orc_params {
     int freeze_flow;       /* pin hook only (no counterpart in the product): 1 keeps the density
                               populations fixed and takes u = 0 and div u = 0 in Eq. (18), so the
                               temperature lattice evolves by conduction through a frozen rho(x) */
+    int wet_mode;          /* bottom wall wettability: 0 neutral (the solid node mirrors the fluid
+                              node above it); 1 virtual density rho_w = phi rho_ave - drho, after
+                              Li, Luo, Kang & Chen (Phys. Rev. E 90, 053301, 2014) */
+    double wet_phi;        /* wet_mode 1, outside the square: rho_w = wet_phi * rho_ave */
+    double wet_phi_in;     /* wet_mode 1, inside the square: rho_w = wet_phi_in * rho_ave - wet_drho */
+    double wet_drho;
+    double wet_square;     /* side of the square centred at ((nx-1)/2, (ny-1)/2); 0: none */
 } orc_params;
 
 typedef struct orc_sim {
@@ -93,6 +101,7 @@ typedef struct orc_sim {
     double *fn, *gn;            /* streamed state for t+1 */
     double *rho, *T, *psi;
     double *Fm, *grho;          /* 3 components, component-major */
+    double *rho_w, *psi_w;      /* virtual density and psi of the solid layer below z = 0 (wet_mode 1) */
     double *uall;               /* u of Eq. (10) at every node (divu_mode 1), component-major */
     double rho_ave;             /* average density used by the next step's buoyancy */
     int status;
@@ -355,6 +364,51 @@ static double bottom_wall_temperature(const orc_params *p, int x, int y) {
  * Whole-grid passes.
  * ------------------------------------------------------------------------- */
 
+/* Whether bottom-wall node (x, y) lies in the centred square. */
+static int in_wet_square(const orc_params *p, int x, int y) {
+    const double cx = 0.5 * (p->nx - 1), cy = 0.5 * (p->ny - 1), h = 0.5 * p->wet_square;
+    return p->wet_square > 0.0 && fabs(x - cx) <= h && fabs(y - cy) <= h;
+}
+
+/* Wettability of the bottom wall (Sec. IV B-C; the paper takes its scheme
+ * from its Ref. [52], which is not reproduced here).  Reading: the virtual-
+ * density scheme of Li, Luo, Kang & Chen (2014).  A solid node x_s of the
+ * layer below z = 0 carries the virtual density
+ *   rho_w = phi * rho_ave - drho,
+ *   rho_ave = sum_a w_a rho(x_s + e_a) s(x_s + e_a) / sum_a w_a s(x_s + e_a),
+ * phi > 1 wetting, phi < 1 or drho > 0 non-wetting (that paper's improved
+ * scheme takes phi = 1, drho > 0 for non-wetting walls; at the density ratio
+ * of 0.86 T_c, rho_l/rho_g = 17, a drho above ~0.1 drives the vapour density
+ * at the wall to zero, so phi < 1 is the usable form here),
+ * s = 1 on fluid nodes: the five neighbours with e_z = +1 (weights 1/18 for
+ * (0,0,1), 1/36 for the four diagonals).  Its psi is Eq. (8) at rho_w and the
+ * temperature of the fluid node above it (reading).  The density gradient
+ * and the force of Eq. (7) at the fluid layer see these virtual values. */
+static void pass_wall_density(orc_sim *s) {
+    const orc_params *p = &s->p;
+    int bad = 0;
+#pragma omp parallel for collapse(2) schedule(static) reduction(| : bad)
+    for (int y = 0; y < p->ny; ++y)
+        for (int x = 0; x < p->nx; ++x) {
+            double num = 0.0, den = 0.0;
+            for (int a = 1; a < Q19; ++a) {
+                if (E19[a][2] != 1) continue;
+                const double w = (E19[a][0] == 0 && E19[a][1] == 0) ? 1.0 / 18.0 : 1.0 / 36.0;
+                const int xn = ((x + E19[a][0]) % p->nx + p->nx) % p->nx;
+                const int yn = ((y + E19[a][1]) % p->ny + p->ny) % p->ny;
+                num += w * s->rho[node_index(p, xn, yn, 0)];
+                den += w;
+            }
+            const double rho_ave = num / den;
+            const double rw = in_wet_square(p, x, y) ? p->wet_phi_in * rho_ave - p->wet_drho : p->wet_phi * rho_ave;
+            const double p2 = psi_squared(p, s->Tc, rw, s->T[node_index(p, x, y, 0)]);
+            if (!(rw > 0.0) || !(p2 >= 0.0)) bad = 1;
+            s->rho_w[(long)y * p->nx + x] = rw;
+            s->psi_w[(long)y * p->nx + x] = sqrt(p2 > 0.0 ? p2 : 0.0);
+        }
+    if (bad) s->status = ORC_EUNSTABLE;
+}
+
 /* Eq. (10) rho = sum f, Eq. (20) T = sum g, Eq. (8) psi. */
 static void pass_macro(orc_sim *s) {
     const long nn = s->nn;
@@ -371,6 +425,7 @@ static void pass_macro(orc_sim *s) {
         s->psi[i] = sqrt(p2 > 0.0 ? p2 : 0.0);
     }
     if (bad) s->status = ORC_EUNSTABLE;
+    if (s->p.bc_z != 0 && s->p.wet_mode == 1) pass_wall_density(s);
 }
 
 /* Eq. (7) interaction force, and the isotropic gradient of rho with the same
@@ -387,9 +442,15 @@ static void pass_stencil(orc_sim *s) {
                 double sp[3] = {0, 0, 0}, sr[3] = {0, 0, 0};
                 for (int a = 1; a < Q19; ++a) {
                     const long j = stencil_neighbour(p, x, y, z, E19[a]);
+                    double pj = s->psi[j], rj = s->rho[j];
+                    if (p->bc_z != 0 && p->wet_mode == 1 && z + E19[a][2] < 0) {
+                        const long k = j % ((long)p->nx * p->ny);  /* (x + e_x, y + e_y) of the solid layer */
+                        pj = s->psi_w[k];
+                        rj = s->rho_w[k];
+                    }
                     for (int c = 0; c < 3; ++c) {
-                        sp[c] += s->omega[a] * s->psi[j] * E19[a][c];
-                        sr[c] += s->omega[a] * s->rho[j] * E19[a][c];
+                        sp[c] += s->omega[a] * pj * E19[a][c];
+                        sr[c] += s->omega[a] * rj * E19[a][c];
                     }
                 }
                 for (int c = 0; c < 3; ++c) {
@@ -597,6 +658,8 @@ static void pass_stream(orc_sim *s) {
                         s->fn[opposite19(a) * nn + i] = s->fs[a * nn + i];
                         continue;
                     } else if (zd > p->nz - 1) {
+                        /* bc_z 2: Eq. (50) bounce-back at the top wall too; bc_z 1: leaves the domain */
+                        if (p->bc_z == 2) s->fn[opposite19(a) * nn + i] = s->fs[a * nn + i];
                         continue;
                     }
                     s->fn[a * nn + node_index(p, xd, yd, zd)] = s->fs[a * nn + i];
@@ -626,7 +689,7 @@ static void pass_stream(orc_sim *s) {
                     if (in_shell(p, x, y, z))
                         for (int a = 0; a < s->QT; ++a) s->gn[a * nn + node_index(p, x, y, z)] = s->wT[a] * p->T_shell;
     }
-    if (walls && !p->freeze_flow) {
+    if (p->bc_z == 1 && !p->freeze_flow) {
         const int zt = p->nz - 1;
         for (int y = 0; y < p->ny; ++y)
             for (int x = 0; x < p->nx; ++x)
@@ -654,14 +717,18 @@ void orc_destroy(orc_sim *s) {
     if (!s) return;
     free(s->f); free(s->g); free(s->phi_prev); free(s->fs); free(s->gp);
     free(s->fn); free(s->gn); free(s->rho); free(s->T); free(s->psi);
-    free(s->Fm); free(s->grho); free(s->uall);
+    free(s->Fm); free(s->grho); free(s->uall); free(s->rho_w); free(s->psi_w);
     free(s);
 }
 
 int orc_create(const orc_params *p, orc_sim **out) {
     *out = NULL;
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return ORC_EINVAL;
+    if (p->bc_z < 0 || p->bc_z > 2) return ORC_EINVAL;
     if (p->bc_z != 0 && p->nz < 3) return ORC_EINVAL;
+    if (p->wet_mode != 0 && (p->wet_mode != 1 || p->bc_z == 0 || !(p->wet_phi > 0.0) || !(p->wet_phi_in > 0.0) ||
+                             !(p->wet_drho >= 0.0) || !(p->wet_square >= 0.0)))
+        return ORC_EINVAL;
     if (p->bc_T_shell && (p->bc_z != 0 || !p->thermal || !(p->T_shell > 0.0))) return ORC_EINVAL;
     if (p->thermal_bgk != 0 && p->thermal_bgk != 1) return ORC_EINVAL;
     /* Reading: the paper gives relaxation rates for the D3Q7 moments only,
@@ -690,8 +757,10 @@ int orc_create(const orc_params *p, orc_sim **out) {
     s->Fm = calloc(3 * nn, sizeof(double));
     s->grho = calloc(3 * nn, sizeof(double));
     s->uall = calloc(p->divu_mode ? 3 * nn : 1, sizeof(double));
+    s->rho_w = calloc((long)p->nx * p->ny, sizeof(double));
+    s->psi_w = calloc((long)p->nx * p->ny, sizeof(double));
     if (!s->f || !s->fs || !s->fn || !s->g || !s->gp || !s->gn || !s->phi_prev || !s->rho || !s->T ||
-        !s->psi || !s->Fm || !s->grho || !s->uall) {
+        !s->psi || !s->Fm || !s->grho || !s->uall || !s->rho_w || !s->psi_w) {
         orc_destroy(s);
         return ORC_ENOMEM;
     }

@@ -22,6 +22,8 @@ def _param_fields(real):
         ("T_wall_patch", real), ("T_wall", real), ("patch_radius", real), ("T_top", real),
         ("thermal", ctypes.c_int), ("bc_T_shell", ctypes.c_int), ("T_shell", real), ("thermal_bgk", ctypes.c_int),
         ("thermal_lattice", ctypes.c_int), ("divu_mode", ctypes.c_int), ("freeze_flow", ctypes.c_int),
+        ("wet_mode", ctypes.c_int), ("wet_phi", real), ("wet_phi_in", real), ("wet_drho", real),
+        ("wet_square", real),
     ]
 
 
@@ -43,7 +45,8 @@ DEFAULTS = dict(nx=8, ny=8, nz=8, bc_z=0, a=2.0 / 49.0, b=2.0 / 21.0, R=1.0, ace
                 G=-1.0, sigma=0.0, tau_e=1.25, tau_v=0.8, tau_q=1.0, tau_pi=1.0, cV=5.0, d=0.95,
                 kappa_mode=0, kappa=0.2, vs_q=1.0, vs_pi=1.0, grav=(0.0, 0.0, 0.0),
                 T_wall_patch=0.0, T_wall=0.0, patch_radius=0.0, T_top=0.0, thermal=1, bc_T_shell=0, T_shell=0.0,
-                thermal_bgk=0, thermal_lattice=0, divu_mode=0, freeze_flow=0)
+                thermal_bgk=0, thermal_lattice=0, divu_mode=0, freeze_flow=0,
+                wet_mode=0, wet_phi=1.0, wet_phi_in=1.0, wet_drho=0.0, wet_square=0.0)
 
 _libs = {}
 

@@ -30,7 +30,7 @@ struct Layout {
     size_t nn, stride, es, rs, cs, planes;
     size_t npop;   // population planes: 19 + velocities of the temperature lattice
     int qt;        // 7 (D3Q7) or 19 (D3Q19)
-    size_t off_pop[2], off_phi, off_stage, off_part, off_scal, total;
+    size_t off_pop[2], off_phi, off_stage, off_part, off_scal, off_wall, total;
     size_t max_partials;
 };
 
@@ -63,8 +63,13 @@ bool valid_params(const lbm_params *p) {
     if ((size_t)p->nx * p->ny * p->nz * element_bytes(p->storage) >= (size_t)1 << 32) return false;
     if ((size_t)p->nx * p->ny * 2 * (element_bytes(p->storage) > 4 ? element_bytes(p->storage) : 4) >= (size_t)1 << 32)
         return false;
-    if (p->bc_z != LBM_BC_PERIODIC && p->bc_z != LBM_BC_WALL_BOTTOM_OPEN_TOP) return false;
-    if (p->bc_z == LBM_BC_WALL_BOTTOM_OPEN_TOP && p->nz < 3) return false;
+    if (p->bc_z != LBM_BC_PERIODIC && p->bc_z != LBM_BC_WALL_BOTTOM_OPEN_TOP && p->bc_z != LBM_BC_WALLS) return false;
+    if (p->bc_z != LBM_BC_PERIODIC && p->nz < 3) return false;
+    if (p->wet_mode != LBM_WET_NEUTRAL && p->wet_mode != LBM_WET_VIRTUAL_DENSITY) return false;
+    if (p->wet_mode == LBM_WET_VIRTUAL_DENSITY &&
+        (p->bc_z == LBM_BC_PERIODIC || !(p->wet_phi > 0.0) || !(p->wet_phi_in > 0.0) || !(p->wet_drho >= 0.0) ||
+         !(p->wet_square >= 0.0)))
+        return false;
     if (!(p->tau_e > 0.5) || !(p->tau_v > 0.5) || !(p->tau_q > 0.5) || !(p->tau_pi > 0.5)) return false;
     if (!(p->vs_q > 0.5) || !(p->vs_pi > 0.5)) return false;
     if (p->G == 0.0 || !(p->cV > 0.0) || !(p->kappa > 0.0)) return false;
@@ -150,6 +155,9 @@ Layout make_layout(const lbm_params *p) {
     off = align_up(off + 2 * L.max_partials * sizeof(double), kAlign);
     L.off_scal = off;
     off = align_up(off + 64 * sizeof(double), kAlign);
+    // virtual density and psi of the solid layer below a bottom wall (walls only)
+    L.off_wall = off;
+    if (p->bc_z != LBM_BC_PERIODIC) off = align_up(off + 2 * (size_t)p->nx * p->ny * sizeof(double), kAlign);
     L.total = off;
     return L;
 }
@@ -208,6 +216,12 @@ lbm::Phys<C> make_phys(const lbm_params *p) {
     P.T_top = p->T_top;
     P.cx = 0.5 * (p->nx - 1);
     P.cy = 0.5 * (p->ny - 1);
+    P.top_wall = p->bc_z == LBM_BC_WALLS;
+    P.wet = p->bc_z != LBM_BC_PERIODIC && p->wet_mode == LBM_WET_VIRTUAL_DENSITY;
+    P.wet_phi = p->wet_phi;
+    P.wet_phi_in = p->wet_phi_in;
+    P.wet_drho = p->wet_drho;
+    P.wet_square = p->wet_square;
     return P;
 }
 
@@ -291,6 +305,7 @@ struct lbm_handle {
     // Device regions: a lattice of its own has them all in its arena; the
     // lattices of a batch share the staging planes and partial sums.
     char *r_pop[2], *r_phi, *r_scal;
+    double *r_wall;   // walls: rho_w and psi_w of the solid layer (null for periodic grids)
     double *r_stage, *r_part;
     int cur;          // which population copy holds the state
     int initialized;
@@ -458,14 +473,21 @@ int step_once(lbm_handle *h) {
     A.nty = (h->p.ny + h->tile_y - 1) / h->tile_y;
     A.cz = h->chunk_z;
     A.P = make_phys<C>(&h->p);
+    A.wall = h->r_wall;
     // u(t) planes of the finite-difference divergence: the staging region
     // (six FP64 planes) holds the three planes in the compute type.
     A.uout = (C *)h->stage();
     A.ustage = A.uout;
     A.unn = h->L.nn;
     const int nb = h->workgroups;
-    int rc = h->p.bc_z == LBM_BC_WALL_BOTTOM_OPEN_TOP ? launch_step_tile<ST, true>(h, A, nb)
-                                                      : launch_step_tile<ST, false>(h, A, nb);
+    if (A.P.wet) {
+        // virtual density of the wall's solid layer from the state at time t
+        const size_t nxy = (size_t)h->p.nx * h->p.ny;
+        hipLaunchKernelGGL(lbm::k_wall_density<ST>, dim3((unsigned)((nxy + 255) / 256)), dim3(256), 0, h->stream,
+                           (const T *)h->pop(c), h->L.stride, h->p.nx, h->p.ny, make_phys<double>(&h->p), h->r_wall,
+                           h->status());
+    }
+    int rc = h->p.bc_z != LBM_BC_PERIODIC ? launch_step_tile<ST, true>(h, A, nb) : launch_step_tile<ST, false>(h, A, nb);
     if (rc) return rc;
     if (A.P.gravity) {
         hipLaunchKernelGGL(lbm::k_finish, dim3(1), dim3(256), 0, h->stream, (const double *)h->partials(), nb, 1, 0,
@@ -563,6 +585,7 @@ int lbm_create(const lbm_params *p, void *dev_arena, size_t arena_bytes, void *h
     h->r_scal = arena + L.off_scal;
     h->r_stage = (double *)(arena + L.off_stage);
     h->r_part = (double *)(arena + L.off_part);
+    h->r_wall = p->bc_z != LBM_BC_PERIODIC ? (double *)(arena + L.off_wall) : nullptr;
     h->cur = 0;
     h->initialized = 0;
     set_default_launch(h);
@@ -656,13 +679,20 @@ int lbm_get_rho_u_T(lbm_handle *h, double *rho, double *ux, double *uy, double *
     const int nb = (int)((nn + 255) / 256);
     const lbm::Phys<double> P = make_phys<double>(&h->p);
     double *st = h->stage();
-    const int walls = h->p.bc_z == LBM_BC_WALL_BOTTOM_OPEN_TOP;
+    const int walls = h->p.bc_z != LBM_BC_PERIODIC;
+    const lbm::Phys<double> Pw = make_phys<double>(&h->p);
     const int lrc = with_format(h->p, [&](auto fmt) {
         using ST = decltype(fmt);
         const typename ST::T *pop = (const typename ST::T *)h->pop(h->cur);
+        if (Pw.wet) {
+            const size_t nxy = (size_t)h->p.nx * h->p.ny;
+            hipLaunchKernelGGL(lbm::k_wall_density<ST>, dim3((unsigned)((nxy + 255) / 256)), dim3(256), 0, h->stream,
+                               pop, h->L.stride, h->p.nx, h->p.ny, Pw, h->r_wall, h->status());
+        }
         hipLaunchKernelGGL(lbm::k_macro<ST>, dim3(nb), dim3(256), 0, h->stream, pop, h->L.stride, nn, P, st);
         hipLaunchKernelGGL(lbm::k_velocity<ST>, dim3(nb), dim3(256), 0, h->stream, pop, h->L.stride, h->p.nx, h->p.ny,
-                           h->p.nz, walls, P, (const double *)h->rho_ave(), st);
+                           h->p.nz, walls, P, (const double *)h->rho_ave(), (const double *)(Pw.wet ? h->r_wall : nullptr),
+                           st);
         return hip_status(hipGetLastError());
     });
     if (lrc) return lrc;
@@ -841,7 +871,8 @@ int lbm_get_launch(const lbm_handle *h, int *tile_x, int *tile_y, int *chunk_z, 
 int lbm_launches_per_step(const lbm_handle *h) {
     if (!h) return 0;
     return ((h->p.g[0] != 0.0 || h->p.g[1] != 0.0 || h->p.g[2] != 0.0) ? 2 : 1) +
-           (h->p.divu_mode == LBM_DIVU_FD ? 1 : 0);
+           (h->p.divu_mode == LBM_DIVU_FD ? 1 : 0) +
+           ((h->p.bc_z != LBM_BC_PERIODIC && h->p.wet_mode == LBM_WET_VIRTUAL_DENSITY) ? 1 : 0);
 }
 
 void lbm_destroy(lbm_handle *h) {
@@ -1001,6 +1032,7 @@ int build_batch_tables(lbm_batch *b) {
         A.status = h->status();
         A.stride = h->L.stride;
         set_buffer_extents(h->L, A.buf_lo_bytes, A.buf_hi_bytes);
+        A.wall = nullptr;    // batches are periodic
         A.ustage = nullptr;  // batches run the local divergence of Eq. (48)
         A.uout = nullptr;
         A.unn = 0;

@@ -92,7 +92,10 @@ struct Phys {
     C T_shell;
     int attract;          // a != 0
     int gravity;          // g != 0
+    int top_wall;         // walls: bounce-back at the top too (closed box) instead of the open top
+    int wet;              // walls: virtual density of the solid layer below z = 0 from the wall buffer
     double T_patch, T_wall, patch_r2, T_top, cx, cy;  // walls (decisions in FP64)
+    double wet_phi, wet_phi_in, wet_drho, wet_square;  // virtual-density scheme of the bottom wall
 };
 
 // psi^2 of Eq. (8) with the Peng-Robinson pressure of Eq. (49).  rho, T and
@@ -313,6 +316,18 @@ struct StoreF16 {
     static constexpr float kScale = 1024.0f;
     __device__ static C dec(T v) { return (float)v; }
     __device__ static T enc(C v) { return (T)v; }
+    // Stochastic rounding (Forsythe, 1959) of a deviation to FP16: the 13
+    // bits of the FP32 significand below the FP16 one are raised by `r`
+    // (uniform in [0, 2^13)) and cut off, so the result is the FP16 neighbour
+    // above |v| with the probability of the cut-off fraction, and the
+    // rounding is unbiased (the conversion of the truncated value is exact
+    // in the normal range).  Round-to-nearest errors of a slowly changing
+    // field stay correlated from step to step and add up: measured on the
+    // 100^3 D^2 test, a 10% error in the late slope that this removes.
+    __device__ static T enc_sr(C v, unsigned r) {
+        const unsigned u = (__builtin_bit_cast(unsigned, v) + (r & 0x1FFFu)) & ~0x1FFFu;
+        return (T)__builtin_bit_cast(float, u);
+    }
     __device__ static C rdec(R v) { return (float)v; }
     __device__ static R renc(C v) { return (R)v; }
     __device__ static double ddec(T v) { return (double)(float)v * (1.0 / 1024.0); }
@@ -334,10 +349,21 @@ struct StoreBF16 {  // conversions round to nearest even (v_cvt_pk_bf16_f32 on g
 
 // A storage format for a temperature lattice of QT = 7 (D3Q7, Sec. III B) or
 // QT = 19 (D3Q19 with the standard weights) velocities.
+template <typename S, typename = void>
+struct HasStochasticRounding : std::false_type {};
+template <typename S>
+struct HasStochasticRounding<S, std::void_t<decltype(S::enc_sr(typename S::C(0), 0u))>> : std::true_type {};
+
 template <typename Base, int QT>
 struct Fmt : Base {
     static_assert(QT == 7 || QT == 19, "temperature lattice");
     static constexpr int kQT = QT;
+    // Encode a value the step stores, with random bits r for formats that
+    // round stochastically (FP16), round-to-nearest otherwise.
+    __device__ static typename Base::T enc_r(typename Base::C v, unsigned r) {
+        if constexpr (HasStochasticRounding<Base>::value) return Base::enc_sr(v, r);
+        else return Base::enc(v);
+    }
 };
 
 // Loads/stores of a 2-, 4- or 8-byte element through a buffer resource.
@@ -572,6 +598,9 @@ struct StepArgs {
     typename ST::T *__restrict__ pop_out;
     typename ST::C *__restrict__ phi;
     const double *__restrict__ rho_ave;
+    // walls with the virtual-density scheme: rho_w (nx*ny values) then psi_w
+    // (nx*ny) of the solid layer below z = 0, written by k_wall_density
+    const double *__restrict__ wall;
     double *__restrict__ partials;  // per-workgroup sum of rho (when gravity is on)
     unsigned *__restrict__ status;
     size_t stride;                  // elements between population planes
@@ -1102,10 +1131,20 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
             if constexpr (DEV) fa[a] = fmad(C(K * w19(a)), rho - own_rref, fs[a]);
             else fa[a] = fs[a] + (a == 0 ? r0 : (a < 7 ? r1 : r2));
         }
+        // Random bits of the stochastic rounding (FP16): a hash of the
+        // node's index in the lattice and of the FP32 bits of its rho and T
+        // (which change from step to step wherever the field evolves), one
+        // draw per stored population.  A function of the node's data only,
+        // so results do not depend on the launch shape.
+        unsigned sr_seed = own;
+        if constexpr (sizeof(C) == 4)
+            sr_seed = (own ^ (__builtin_bit_cast(unsigned, rho) * 0x9E3779B1u)) ^
+                      (__builtin_bit_cast(unsigned, T) * 0x85EBCA77u);
+        auto srb = [&](int a) -> unsigned { return ((sr_seed ^ (0x9E3779B9u * (unsigned)(a + 1))) * 0x7FEB352Du) >> 19; };
         auto fval = [&](int a, int slot, int dx, int dy) -> E {
             if constexpr (DEV) {
                 const C bd = rref(slot, li + dy * EX + dx);
-                return ST::enc(fmad(C(K * w19(a)), own_rref - bd, fa[a]));
+                return ST::enc_r(fmad(C(K * w19(a)), own_rref - bd, fa[a]), srb(a));
             } else {
                 return ST::enc(fa[a]);
             }
@@ -1152,7 +1191,8 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
                 const int ex = kE19X[a], ey = kE19Y[a], ez = kE19Z[a];
                 const bool to_shell = xs[ex + 1] || ys[ey + 1] || zs[ez + 1];
                 io.store_pair(LY::pair_of(a), Yo[ey + 1] + Xo[ex + 1], Zo[ez + 1],
-                              word(fval(a, sl[ez + 1], ex, ey), ST::enc(gval(a, sl[ez + 1], ex, ey, to_shell))));
+                              word(fval(a, sl[ez + 1], ex, ey),
+                                   ST::enc_r(gval(a, sl[ez + 1], ex, ey, to_shell), srb(G0 + a))));
             }
 #pragma unroll
             for (int a = QT; a < 19; ++a) {
@@ -1175,11 +1215,14 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
                 const unsigned inrow = Yo[ey + 1] + Xo[ex + 1];
                 if (WALLS) {
                     if (ez < 0 && z == 0) {  // Eq. (50): halfway bounce-back into the own node
-                        io.store(opposite(a), rowb, Zc, ST::enc(fa[a]));
+                        io.store(opposite(a), rowb, Zc, ST::enc_r(fa[a], srb(a)));
                         continue;
                     }
-                    if (ez > 0 && z == nz - 1) continue;  // leaves through the open top
-                    if (ez < 0 && z == nz - 1)             // open top: unknown f copied from below
+                    if (ez > 0 && z == nz - 1) {  // Eq. (50) at a top wall, or out through the open top
+                        if (P.top_wall) io.store(opposite(a), rowb, Zc, ST::enc_r(fa[a], srb(a)));
+                        continue;
+                    }
+                    if (ez < 0 && z == nz - 1 && !P.top_wall)  // open top: unknown f copied from below
                         io.store(a, inrow, Zc, fval(a, s0, ex, ey));
                 }
                 io.store(a, inrow, Zo[ez + 1], fval(a, sl[ez + 1], ex, ey));
@@ -1195,19 +1238,20 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
                             const C Tw = bottom ? T_bottom : (C)P.T_top;
                             const C v = DEV ? fmad(K * wg(a), C(2) * Tw - T - own_tref, -gs[a])
                                             : fmad(C(2) * wg(a), Tw, -ga[a]);
-                            io.store(G0 + opposite(a), rowb, Zc, ST::enc(v));
+                            io.store(G0 + opposite(a), rowb, Zc, ST::enc_r(v, srb(G0 + a)));
                             continue;
                         }
                     }
                     const bool to_shell = xs[ex + 1] || ys[ey + 1] || zs[ez + 1];
-                    io.store(G0 + a, Yo[ey + 1] + Xo[ex + 1], Zo[ez + 1], ST::enc(gval(a, sl[ez + 1], ex, ey, to_shell)));
+                    io.store(G0 + a, Yo[ey + 1] + Xo[ex + 1], Zo[ez + 1],
+                             ST::enc_r(gval(a, sl[ez + 1], ex, ey, to_shell), srb(G0 + a)));
                 }
             } else {
                 // temperature held fixed: g stays at the node (re-encoded against the new reference)
     #pragma unroll
                 for (int a = 0; a < QT; ++a) {
                     const C v = DEV ? fmad(K * wg(a), nd.bt - own_tref, nd.r[a]) : nd.r[a];
-                    io.store(G0 + a, rowb, Zc, ST::enc(v));
+                    io.store(G0 + a, rowb, Zc, ST::enc_r(v, srb(G0 + a)));
                 }
             }
             if constexpr (DEV) {
@@ -1269,6 +1313,17 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         load_plane(z0, cur, h0);
         load_plane(z0 + 1, nxt, nxh);
         plane_moments(0, t0, th0, a0, a1, a2);
+        if (WALLS && P.wet && z0 == 0) {
+            // The solid layer below z = 0 holds the virtual density and its
+            // psi (k_wall_density) instead of a copy of the layer above.
+            const unsigned nxy = plane;
+            s_rho[0][li] = (C)A.wall[irow];
+            s_psi[0][li] = (C)A.wall[nxy + irow];
+            if (has_halo) {
+                s_rho[0][hli] = (C)A.wall[hrow];
+                s_psi[0][hli] = (C)A.wall[nxy + hrow];
+            }
+        }
         plane_moments(1, cur, h0, c_rho, c_T, c_psi);
         if constexpr (DFD) {
             plane_velocity(0, z0 - 1);
@@ -1442,6 +1497,52 @@ __global__ void __launch_bounds__(256) k_init(const double *__restrict__ stage, 
     phi[i] = typename ST::C(0);
 }
 
+// Wettability of the bottom wall: the virtual density of each solid node of
+// the layer below z = 0, rho_w = phi rho_ave - drho with rho_ave the weighted
+// mean of its five fluid neighbours (e_z = +1; weights 1/18 and 1/36), phi
+// and drho those of the centred square or of the rest of the wall, and
+// psi_w of Eq. (8) at rho_w and the temperature of the fluid node above it.
+// Evaluated in FP64 from the state at time t (before the step, and before
+// the readout); sets status bit 1 where rho_w <= 0 or psi_w^2 < 0.
+template <typename ST>
+__global__ void __launch_bounds__(256) k_wall_density(const typename ST::T *__restrict__ pop, size_t st, int nx,
+                                                      int ny, Phys<double> P, double *__restrict__ wall,
+                                                      unsigned *__restrict__ status) {
+    const size_t nxy = (size_t)nx * ny;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nxy) return;
+    const int x = (int)(i % nx), y = (int)(i / nx);
+    const NodeView<ST> v{pop, st};
+    constexpr int QT = ST::kQT;
+    auto rho_at = [&](size_t j) {
+        double fl[19];
+#pragma unroll
+        for (int a = 0; a < 19; ++a) fl[a] = v.e(a, j);
+        return v.ref(0, j) + sum19(fl);
+    };
+    double num = 0.0, den = 0.0;
+#pragma unroll
+    for (int a = 1; a < 19; ++a) {
+        if (kE19Z[a] != 1) continue;
+        const double w = (kE19X[a] == 0 && kE19Y[a] == 0) ? 1.0 / 18.0 : 1.0 / 36.0;
+        const int xn = (x + kE19X[a] + nx) % nx, yn = (y + kE19Y[a] + ny) % ny;
+        num += w * rho_at((size_t)yn * nx + xn);
+        den += w;
+    }
+    double gl[QT];
+#pragma unroll
+    for (int a = 0; a < QT; ++a) gl[a] = v.e(19 + a, i);
+    const double T = v.ref(1, i) + sum_T<QT>(gl);
+    const double rho_ave = num / den;
+    const double h = 0.5 * P.wet_square;
+    const bool in_square = P.wet_square > 0.0 && fabs(x - P.cx) <= h && fabs(y - P.cy) <= h;
+    const double rw = in_square ? P.wet_phi_in * rho_ave - P.wet_drho : P.wet_phi * rho_ave;
+    const double p2 = psi_squared(P, rw, T);
+    if (!(rw > 0.0) || !(p2 >= 0.0)) atomicOr(status, 1u);
+    wall[i] = rw;
+    wall[nxy + i] = ::sqrt(p2 > 0.0 ? p2 : 0.0);
+}
+
 // Per-node rho, T (and psi) in FP64 into the staging planes 0, 4, 5.
 template <typename ST>
 __global__ void __launch_bounds__(256) k_macro(const typename ST::T *__restrict__ pop, size_t st, size_t nn,
@@ -1463,10 +1564,14 @@ __global__ void __launch_bounds__(256) k_macro(const typename ST::T *__restrict_
 }
 
 // u of Eq. (10) with the total force, in FP64, into staging planes 1..3.
+// With walls, a solid neighbour below z = 0 contributes psi_w from `wall`
+// (virtual-density wetting) or, if `wall` is null, the psi of the fluid node
+// above it.
 template <typename ST>
 __global__ void __launch_bounds__(256) k_velocity(const typename ST::T *__restrict__ pop, size_t st, int nx, int ny,
                                                   int nz, int walls, Phys<double> P,
-                                                  const double *__restrict__ rho_ave, double *__restrict__ stage) {
+                                                  const double *__restrict__ rho_ave, const double *__restrict__ wall,
+                                                  double *__restrict__ stage) {
     const size_t nn = (size_t)nx * ny * nz;
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nn) return;
@@ -1480,7 +1585,9 @@ __global__ void __launch_bounds__(256) k_velocity(const typename ST::T *__restri
         if (walls) zn = zn < 0 ? 0 : (zn > nz - 1 ? nz - 1 : zn);
         else zn = (zn + nz) % nz;
         const double w = (kE19X[a] * kE19X[a] + kE19Y[a] * kE19Y[a] + kE19Z[a] * kE19Z[a]) == 1 ? 1.0 / 6.0 : 1.0 / 12.0;
-        const double val = w * psi[((size_t)zn * ny + yn) * nx + xn];
+        const bool solid_below = walls && wall && z + kE19Z[a] < 0;
+        const double val = w * (solid_below ? wall[(size_t)nx * ny + (size_t)yn * nx + xn]
+                                            : psi[((size_t)zn * ny + yn) * nx + xn]);
         Sp[0] += val * kE19X[a];
         Sp[1] += val * kE19Y[a];
         Sp[2] += val * kE19Z[a];

@@ -14,7 +14,8 @@ import numpy as np
 from . import build as _build
 
 OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, ESTATE, ESCRATCH = 0, -1, -2, -3, -4, -5, -6
-BC_PERIODIC, BC_WALL_BOTTOM_OPEN_TOP = 0, 1
+BC_PERIODIC, BC_WALL_BOTTOM_OPEN_TOP, BC_WALLS = 0, 1, 2
+WET_NEUTRAL, WET_VIRTUAL_DENSITY = 0, 1
 KAPPA_CONST_LAMBDA, KAPPA_CONST_CHI = 0, 1
 STORE_F32, STORE_F64, STORE_F16, STORE_BF16, STORE_F32_DEV = 0, 1, 2, 3, 4
 _STORAGE_NAMES = {"f32": STORE_F32, "f64": STORE_F64, "f16": STORE_F16, "bf16": STORE_BF16,
@@ -36,6 +37,8 @@ class LbmParams(ctypes.Structure):
         ("thermal", ctypes.c_int), ("storage", ctypes.c_int),
         ("bc_T_shell", ctypes.c_int), ("T_shell", ctypes.c_double), ("thermal_bgk", ctypes.c_int),
         ("thermal_lattice", ctypes.c_int), ("divu_mode", ctypes.c_int),
+        ("wet_mode", ctypes.c_int), ("wet_phi", ctypes.c_double), ("wet_phi_in", ctypes.c_double),
+        ("wet_drho", ctypes.c_double), ("wet_square", ctypes.c_double),
     ]
 
 
@@ -129,6 +132,11 @@ def make_params(params: dict, storage="f32") -> LbmParams:
     src.setdefault("thermal_bgk", 0)
     src.setdefault("thermal_lattice", 0)
     src.setdefault("divu_mode", 0)
+    src.setdefault("wet_mode", 0)
+    src.setdefault("wet_phi", 1.0)
+    src.setdefault("wet_phi_in", 1.0)
+    src.setdefault("wet_drho", 0.0)
+    src.setdefault("wet_square", 0.0)
     for n in names:
         if n not in src:
             raise KeyError(f"missing parameter {n!r}")

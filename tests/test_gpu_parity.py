@@ -32,6 +32,7 @@ FP32_U_BOUND = {
     "d3q19/flat_interface_128/200": 2.7e-5,    # 1.39e-5 (3.8e-5)
     "f32dev/static_droplet_32/300": 4.1e-5,    # 2.07e-5 (3.1e-4)
     "f32dev/flat_interface_128/200": 2.8e-5,   # 1.44e-5 (7.6e-5)
+    "wetting/closed/60": 2.6e-5,               # 1.30e-5
 }
 
 
@@ -348,3 +349,52 @@ def test_fd_divergence_launch_shapes(storage):
     assert lat.launches_per_step() == 2
     lat.close()
 
+
+
+# Walls with the virtual-density wettability (a hydrophobic square in a
+# hydrophilic wall, Sec. IV C's pattern) under the open top and in the closed
+# box of Sec. IV C (bounce-back at the top too), with gravity and the heated
+# wall.
+def _wet_case(closed):
+    from oracle import thermo
+    Tc = thermo.critical_temperature(2.0 / 49.0, 2.0 / 21.0, 1.0)
+    w = workload("pool_boiling_32x32x48", wet_mode=1, wet_phi=1.3, wet_phi_in=0.8, wet_square=13.0,
+                 T_wall_patch=0.96 * Tc, T_wall=0.93 * Tc, patch_radius=9.0)
+    if closed:
+        w["params"].update(bc_z=2, nz=40)
+        w["init"]["depth"] = 28.0
+    return w
+
+
+@pytest.mark.parametrize("closed", [False, True], ids=["open_top", "closed_box"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_wetting_walls_against_oracle(storage, closed):
+    w = _wet_case(closed)
+    steps = 60
+    _say(f"wetting walls closed={closed} {storage} steps={steps}")
+    ref = run_oracle(w, steps)
+    e = errors(run_gpu(w, steps, storage, chunks=[1, 29, 30]), ref)
+    _say(f"  errors {e}")
+    if storage == "f64":
+        _check(e, FP64_TOL)
+    elif storage == "f32":
+        check_fp32(f"wetting/{'closed' if closed else 'open'}/{steps}", w, steps, e, ref)
+    else:
+        tol = DEV_TOL["f16"]
+        assert e["rho"] <= tol and e["T"] <= tol and e["u_l2"] <= 20 * tol, e
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_wetting_walls_launch_shape_bitwise(storage):
+    """The solid layer's virtual density reaches every tile and halo node
+    (ragged tiles put tile edges on the wall's square and the patch)."""
+    w = _wet_case(True)
+    w["params"].update(nx=40, ny=36, nz=20)
+    w["init"]["depth"] = 12.0
+    outs = []
+    for launch in [(64, 8, 4), (32, 8, 7), (128, 4, 20), (32, 16, 1)]:
+        _say(f"wetting {storage} launch {launch}")
+        outs.append(run_gpu(w, 25, storage, launch=launch))
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
