@@ -330,14 +330,18 @@ int hip_status(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EHIP; }
 // Default launch shape (measured on MI355X): 64x8 tiles where the rows are
 // long enough (their halo is 29% of the tile against 52% for 128x4 or 64x4;
 // FP32 at 128^3 / 192^3 / 256^3 / the 256x256x384 pool: 1-13% faster than
-// 128x4 tiles, FP16 2-4% faster than 32x16 except at 128^3), and chunks of
-// 16-32 planes; the z halo of a chunk is read twice, so chunks are kept long
-// unless the grid would then give fewer workgroups than the 256 compute
-// units.
+// 128x4 tiles, FP16 2-4% faster than 32x16 except at 128^3; at 512^3 16-bit
+// storage runs 2% faster in whole 128-node rows), and chunks of up to 64
+// planes; the z halo of a chunk is read twice, so chunks are kept long
+// (64 planes: 2-3% faster than 32 at 512^3 and on the pool) unless the grid
+// would then give fewer workgroups than the 256 compute units.
 void set_default_launch(lbm_handle *h) {
     const int nx = h->p.nx, ny = h->p.ny, nz = h->p.nz;
     const bool half = h->L.es == 2;
-    if (nx >= 64) {
+    if (half && nx >= 512) {
+        h->tile_x = 128;
+        h->tile_y = 4;
+    } else if (nx >= 64) {
         h->tile_x = 64;
         h->tile_y = 8;
     } else if (nx > 32) {
@@ -360,7 +364,7 @@ void set_default_launch(lbm_handle *h) {
     }
     const long tiles = (long)((nx + h->tile_x - 1) / h->tile_x) * ((ny + h->tile_y - 1) / h->tile_y);
     long cz = (long)nz * tiles / 256;
-    if (cz > 32) cz = 32;
+    if (cz > 64) cz = 64;
     if (cz < 4) cz = 4;
     if (cz > nz) cz = nz;
     h->chunk_z = (int)cz;

@@ -324,8 +324,9 @@ struct StoreF16 {
     // in the normal range).  Round-to-nearest errors of a slowly changing
     // field stay correlated from step to step and add up: measured on the
     // 100^3 D^2 test, a 10% error in the late slope that this removes.
+    // `r` is 32 random bits; the top 13 are used.
     __device__ static T enc_sr(C v, unsigned r) {
-        const unsigned u = (__builtin_bit_cast(unsigned, v) + (r & 0x1FFFu)) & ~0x1FFFu;
+        const unsigned u = (__builtin_bit_cast(unsigned, v) + (r >> 19)) & ~0x1FFFu;
         return (T)__builtin_bit_cast(float, u);
     }
     __device__ static C rdec(R v) { return (float)v; }
@@ -341,6 +342,12 @@ struct StoreBF16 {  // conversions round to nearest even (v_cvt_pk_bf16_f32 on g
     static constexpr float kScale = 1.0f;
     __device__ static C dec(T v) { return (float)v; }
     __device__ static T enc(C v) { return (T)v; }
+    // Stochastic rounding as for FP16, on the 16 bits below the BF16
+    // significand (the top 16 of the 32 random bits `r`).
+    __device__ static T enc_sr(C v, unsigned r) {
+        const unsigned u = (__builtin_bit_cast(unsigned, v) + (r >> 16)) & 0xFFFF0000u;
+        return (T)__builtin_bit_cast(float, u);
+    }
     __device__ static C rdec(R v) { return v; }
     __device__ static R renc(C v) { return v; }
     __device__ static double ddec(T v) { return (double)(float)v; }
@@ -359,7 +366,7 @@ struct Fmt : Base {
     static_assert(QT == 7 || QT == 19, "temperature lattice");
     static constexpr int kQT = QT;
     // Encode a value the step stores, with random bits r for formats that
-    // round stochastically (FP16), round-to-nearest otherwise.
+    // round stochastically (FP16, BF16), round-to-nearest otherwise.
     __device__ static typename Base::T enc_r(typename Base::C v, unsigned r) {
         if constexpr (HasStochasticRounding<Base>::value) return Base::enc_sr(v, r);
         else return Base::enc(v);
@@ -1131,7 +1138,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
             if constexpr (DEV) fa[a] = fmad(C(K * w19(a)), rho - own_rref, fs[a]);
             else fa[a] = fs[a] + (a == 0 ? r0 : (a < 7 ? r1 : r2));
         }
-        // Random bits of the stochastic rounding (FP16): a hash of the
+        // Random bits of the stochastic rounding (FP16, BF16): a hash of the
         // node's index in the lattice and of the FP32 bits of its rho and T
         // (which change from step to step wherever the field evolves), one
         // draw per stored population.  A function of the node's data only,
@@ -1140,7 +1147,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         if constexpr (sizeof(C) == 4)
             sr_seed = (own ^ (__builtin_bit_cast(unsigned, rho) * 0x9E3779B1u)) ^
                       (__builtin_bit_cast(unsigned, T) * 0x85EBCA77u);
-        auto srb = [&](int a) -> unsigned { return ((sr_seed ^ (0x9E3779B9u * (unsigned)(a + 1))) * 0x7FEB352Du) >> 19; };
+        auto srb = [&](int a) -> unsigned { return (sr_seed ^ (0x9E3779B9u * (unsigned)(a + 1))) * 0x7FEB352Du; };
         auto fval = [&](int a, int slot, int dx, int dy) -> E {
             if constexpr (DEV) {
                 const C bd = rref(slot, li + dy * EX + dx);

@@ -3,10 +3,11 @@ validates the method with: coexistence densities of a flat slab, the Laplace pre
 a static droplet, and the D^2 slope of an evaporating droplet (Sec. IV A).
 
 Reference values come from tests/golden/precision_refs.json, written by the
-oracle alone (tests/golden/make_precision_refs.py).  FP32 (plain and
-deviation) and FP16 deviation storage must match each within 1e-3 relative.
-BF16 keeps 8 significand bits: it is held to the coexistence densities only
-(its Laplace jump and D^2 slope are reported, not asserted)."""
+oracle alone (tests/golden/make_precision_refs.py).  Every storage format
+must match each within 1e-3 relative: FP32 (plain and deviation), and the
+FP16 and BF16 deviations, which are rounded stochastically (with
+round-to-nearest BF16 missed the Laplace jump by 4e-3 and the D^2 slope by
+4e-2, measured)."""
 import json
 import os
 
@@ -18,7 +19,6 @@ import precision_metrics as PM
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-3
-BF16_COEX_TOL = 2e-3
 
 with open(os.path.join(GOLDEN, "precision_refs.json")) as fh:
     REFS = json.load(fh)["cases"]
@@ -40,8 +40,4 @@ def test_derived_quantities_match_oracle(case, storage):
     got = PM.run_case(case, gpu_runner(storage))
     err = PM.relative_errors(case, got, REFS[case])
     print(f"  {case} {storage} relative errors {err}", flush=True)
-    if storage == "bf16":
-        if case == "coexistence":
-            assert max(err.values()) <= BF16_COEX_TOL, err
-        return
     assert max(err.values()) <= TOL, err
