@@ -313,7 +313,8 @@ void lbm_batch_destroy(lbm_batch *b);
 /* ---------------------------------------------------------------------------
  * Measurement aid (not part of the model): copy `bytes` bytes (a multiple of
  * 16; both pointers 16-byte aligned device memory, not overlapping) with a
- * plain streaming kernel of 16-byte loads and stores, enqueued on the stream
+ * plain streaming kernel (one 16-byte non-temporal load and store a
+ * thread), enqueued on the stream
  * without blocking.  Its rate is the practical HBM ceiling the step kernels
  * are compared with, and its known traffic calibrates the hardware counters.
  * EINVAL on a bad argument.
