@@ -562,15 +562,21 @@ def main():
         out["divergence_comparison"] = dict(
             workload="evaporation_128", **divergence_comparison(lbm, w128["params"], f128, 250, 20))
     if not args.no_precision and extras:
-        errs = precision_errors(args.storage)
-        print(f"# precision of {args.storage}: {errs}", file=sys.stderr, flush=True)
-        prec = {"storage": args.storage, "reference": "FP64 oracle", "bound": PRECISION_BOUND, "cases": errs}
-        if not args.no_d2_full_size:
-            prec["d2_100"] = d2_full_size(lbm, W, (args.storage,))
-        flags = [c["within_bound"] for c in errs.values()]
-        if "d2_100" in prec:
-            flags += [v[args.storage] for win in prec["d2_100"]["windows"].values() for v in [win["within_bound"]]]
-        prec["within_bound"] = all(flags)
+        # the timed storage and the comparison storage, each against the oracle
+        stores = [args.storage] + ([args.compare] if args.compare not in ("none", args.storage) else [])
+        prec = {"storage": args.storage, "reference": "FP64 oracle", "bound": PRECISION_BOUND}
+        d2 = d2_full_size(lbm, W, tuple(stores)) if not args.no_d2_full_size else None
+        for st in stores:
+            errs = precision_errors(st)
+            print(f"# precision of {st}: {errs}", file=sys.stderr, flush=True)
+            flags = [c["within_bound"] for c in errs.values()]
+            if d2:
+                flags += [win["within_bound"][st] for win in d2["windows"].values()]
+            key = "cases" if st == args.storage else f"compare_{st}"
+            prec[key] = errs
+            prec["within_bound" if st == args.storage else f"compare_{st}_within_bound"] = all(flags)
+        if d2:
+            prec["d2_100"] = d2
         out["precision"] = prec
     if not args.no_batch and extras:
         bl = tuple(int(v) for v in args.batch_launch.split("x")) if args.batch_launch else None

@@ -217,3 +217,37 @@ def test_step_graph_replay_equals_direct_launches(case):
             assert np.array_equal(a, b), (case, k, n)
     for lat in lats:
         lat.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_degenerate_grids_and_zero_steps(storage):
+    """A single node (every neighbour is the node itself, so F_m = 0 and the
+    state is a fixed point of the uniform solution), a 1 x 1 x 3 column with
+    walls (the smallest wall grid), and lbm_step(0), which must leave the
+    state untouched, against the oracle."""
+    from paper_2201_06039_amd import lbm
+    from oracle import sim
+    cases = [workload("static_droplet_32", nx=1, ny=1, nz=1, radius=0.2),
+             workload("pool_boiling_32x32x48", nx=1, ny=1, nz=3, depth=1.5, patch_radius=0.0)]
+    for w in cases:
+        p = w["params"]
+        print(f"degenerate {p['nx']}x{p['ny']}x{p['nz']} bc_z={p['bc_z']} {storage}", flush=True)
+        fields = W.fields(w)
+        lat = lbm.Lattice(p, storage=storage, device="cuda:0")
+        lat.init_fields(*fields)
+        blob = lat.get_state()
+        lat.step(0)
+        assert lat.get_state() == blob
+        lat.step(7)
+        got = lat.rho_u_T()
+        lat.close()
+        s = sim.Sim(**p)
+        s.init_fields(*fields)
+        s.step(7)
+        ref = s.rho_u_T()
+        s.close()
+        tol = {"f64": 1e-12, "f32": 1e-5, "f16": 2.0 ** -11}[storage]
+        for k in (0, 4):
+            assert np.abs(got[k] - ref[k]).max() <= tol * np.abs(ref[k]).max(), (k, got[k], ref[k])
+        du = max(np.abs(got[c] - ref[c]).max() for c in (1, 2, 3))
+        assert du <= max(tol, 1e-12) * max(1.0, max(np.abs(ref[c]).max() for c in (1, 2, 3))), du
