@@ -249,6 +249,20 @@ __device__ __forceinline__ void equilibrium19(C rho, C ux, C uy, C uz, C *meq) {
 __device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// The word holding a pair of T, and packing/unpacking of its halves.
+template <typename T>
+using PairWord = std::conditional_t<sizeof(T) == 2, unsigned, unsigned long long>;
+template <typename T>
+__device__ __forceinline__ PairWord<T> pack_pair(T lo, T hi) {
+    using H = std::conditional_t<sizeof(T) == 2, unsigned short, unsigned>;
+    return (PairWord<T>)__builtin_bit_cast(H, lo) | ((PairWord<T>)__builtin_bit_cast(H, hi) << (8 * sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ T pair_half(PairWord<T> w, int h) {
+    using H = std::conditional_t<sizeof(T) == 2, unsigned short, unsigned>;
+    return __builtin_bit_cast(T, (H)(h ? w >> (8 * sizeof(T)) : w));
+}
+
 // ---------------------------------------------------------------------------
 // Storage formats of the populations.
 // ---------------------------------------------------------------------------
@@ -318,16 +332,21 @@ struct StoreF16 {
     __device__ static T enc(C v) { return (T)v; }
     // Stochastic rounding (Forsythe, 1959) of a deviation to FP16: the 13
     // bits of the FP32 significand below the FP16 one are raised by `r`
-    // (uniform in [0, 2^13)) and cut off, so the result is the FP16 neighbour
-    // above |v| with the probability of the cut-off fraction, and the
-    // rounding is unbiased (the conversion of the truncated value is exact
-    // in the normal range).  Round-to-nearest errors of a slowly changing
-    // field stay correlated from step to step and add up: measured on the
-    // 100^3 D^2 test, a 10% error in the late slope that this removes.
-    // `r` is 32 random bits; the top 13 are used.
+    // (uniform in [0, 2^13)) and the conversion rounds toward zero, so the
+    // result is the FP16 neighbour above |v| with the probability of the
+    // cut-off fraction, and the rounding is unbiased in the normal range.
+    // Round-to-nearest errors of a slowly changing field stay correlated
+    // from step to step and add up: measured on the 100^3 D^2 test, a 10%
+    // error in the late slope that this removes.  One packing conversion
+    // (v_cvt_pkrtz_f16_f32) rounds two values.
+    static constexpr int kSrBits = 13;
+    __device__ static unsigned enc_pair_sr(C v0, unsigned r0, C v1, unsigned r1) {
+        const float u0 = __builtin_bit_cast(float, __builtin_bit_cast(unsigned, v0) + r0);
+        const float u1 = __builtin_bit_cast(float, __builtin_bit_cast(unsigned, v1) + r1);
+        return __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(u0, u1));
+    }
     __device__ static T enc_sr(C v, unsigned r) {
-        const unsigned u = (__builtin_bit_cast(unsigned, v) + (r >> 19)) & ~0x1FFFu;
-        return (T)__builtin_bit_cast(float, u);
+        return __builtin_bit_cast(T, (unsigned short)enc_pair_sr(v, r, v, r));
     }
     __device__ static C rdec(R v) { return (float)v; }
     __device__ static R renc(C v) { return (R)v; }
@@ -343,10 +362,15 @@ struct StoreBF16 {  // conversions round to nearest even (v_cvt_pk_bf16_f32 on g
     __device__ static C dec(T v) { return (float)v; }
     __device__ static T enc(C v) { return (T)v; }
     // Stochastic rounding as for FP16, on the 16 bits below the BF16
-    // significand (the top 16 of the 32 random bits `r`).
+    // significand (r uniform in [0, 2^16)); the BF16 value is the upper half
+    // of the raised FP32 bits.
+    static constexpr int kSrBits = 16;
+    __device__ static unsigned enc_pair_sr(C v0, unsigned r0, C v1, unsigned r1) {
+        const unsigned u0 = __builtin_bit_cast(unsigned, v0) + r0, u1 = __builtin_bit_cast(unsigned, v1) + r1;
+        return (u0 >> 16) | (u1 & 0xFFFF0000u);
+    }
     __device__ static T enc_sr(C v, unsigned r) {
-        const unsigned u = (__builtin_bit_cast(unsigned, v) + (r >> 16)) & 0xFFFF0000u;
-        return (T)__builtin_bit_cast(float, u);
+        return __builtin_bit_cast(T, (unsigned short)((__builtin_bit_cast(unsigned, v) + r) >> 16));
     }
     __device__ static C rdec(R v) { return v; }
     __device__ static R renc(C v) { return v; }
@@ -365,11 +389,17 @@ template <typename Base, int QT>
 struct Fmt : Base {
     static_assert(QT == 7 || QT == 19, "temperature lattice");
     static constexpr int kQT = QT;
-    // Encode a value the step stores, with random bits r for formats that
-    // round stochastically (FP16, BF16), round-to-nearest otherwise.
+    // Encode a value the step stores, with random bits r (uniform in
+    // [0, 2^kSrBits)) for formats that round stochastically (FP16, BF16),
+    // round-to-nearest otherwise; enc_pair_r encodes the two halves of a
+    // word of the paired layout.
     __device__ static typename Base::T enc_r(typename Base::C v, unsigned r) {
         if constexpr (HasStochasticRounding<Base>::value) return Base::enc_sr(v, r);
         else return Base::enc(v);
+    }
+    __device__ static auto enc_pair_r(typename Base::C v0, unsigned r0, typename Base::C v1, unsigned r1) {
+        if constexpr (HasStochasticRounding<Base>::value) return Base::enc_pair_sr(v0, r0, v1, r1);
+        else return pack_pair<typename Base::T>(Base::enc(v0), Base::enc(v1));
     }
 };
 
@@ -421,20 +451,6 @@ constexpr int kBufferFlags = 0x00020000;  // raw dword buffer; the record count 
 //  BUF = false: plain global pointers (any size).
 template <typename T>
 constexpr bool paired_layout() { return sizeof(T) == 2 || sizeof(T) == 4; }
-
-// The word holding a pair of T, and packing/unpacking of its halves.
-template <typename T>
-using PairWord = std::conditional_t<sizeof(T) == 2, unsigned, unsigned long long>;
-template <typename T>
-__device__ __forceinline__ PairWord<T> pack_pair(T lo, T hi) {
-    using H = std::conditional_t<sizeof(T) == 2, unsigned short, unsigned>;
-    return (PairWord<T>)__builtin_bit_cast(H, lo) | ((PairWord<T>)__builtin_bit_cast(H, hi) << (8 * sizeof(T)));
-}
-template <typename T>
-__device__ __forceinline__ T pair_half(PairWord<T> w, int h) {
-    using H = std::conditional_t<sizeof(T) == 2, unsigned short, unsigned>;
-    return __builtin_bit_cast(T, (H)(h ? w >> (8 * sizeof(T)) : w));
-}
 
 // Population planes of a copy for a temperature lattice of QT = 7 (D3Q7) or
 // 19 (D3Q19) velocities: f_0..f_18 are planes 0..18, g_0..g_{QT-1} follow
@@ -689,18 +705,29 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     __shared__ C s_tref[TS][TN];  // the references every node writes for itself
     __shared__ double s_red[NT / 64];
 
+    // STASH (4-byte elements): the tile node's words of plane z+1 wait in LDS
+    // from its moments until its collision, instead of occupying registers
+    // across the collision of plane z (each thread reads back only its own
+    // entries, so no barrier guards them).  Measured at 512^3: FP32 6% faster;
+    // FP16, whose words take half the registers, 3% slower.
+    constexpr bool STASH = paired_layout<E>() && sizeof(E) == 4;
     // The float constants of the model are read by vector instructions in
     // every iteration; held in scalar registers they exceed the scalar
     // register file and are spilled to vector lanes, costing one read per use.
     // Keeping them in vector registers from the start (the empty asm only
-    // tells the compiler they live there) avoids that.
+    // tells the compiler they live there) avoids that.  With the stash only
+    // the constants of the temperature lattice (divu_a .. gam_pi, bits 12-20
+    // of the mask below) are pinned; pinning all of them then costs more
+    // registers than the spills it saves (measured: FP32 64x8 tiles).
+    constexpr unsigned kConstInVgpr = STASH ? 0x1FF000u : 0x1FFFFFFu;
     Phys<C> P = A.P;
     if constexpr (sizeof(C) == 4) {
         C *v[] = {&P.a, &P.b, &P.R, &P.kap, &P.inv_Tc, &P.two_over_Gc2, &P.negG, &P.sig6, &P.lam_e, &P.lam_v,
                   &P.lam_q, &P.lam_pi, &P.divu_a, &P.divu_b, &P.inv_cV, &P.wT0, &P.wT1, &P.inv_csT2, &P.kappa,
                   &P.gam_q, &P.gam_pi, &P.gx, &P.gy, &P.gz, &P.T_shell};
 #pragma unroll
-        for (C *q : v) asm("" : "+v"(*q));
+        for (int i = 0; i < 25; ++i)
+            if ((kConstInVgpr >> i) & 1) asm("" : "+v"(*v[i]));
     }
     const int nx = A.nx, ny = A.ny, nz = A.nz;
     const unsigned plane = (unsigned)nx * (unsigned)ny;
@@ -813,6 +840,31 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     //   2: after the collision (FP16 with the D3Q19 temperature lattice).
     Node cur, nxt, nxh, nq;
     constexpr int HALO_AT = (QT == 19 && sizeof(E) == 2) ? 2 : 1;
+    __shared__ PairWord<E> s_node[STASH ? WORDS : 1][STASH ? NT : 1];
+    __shared__ C s_nref[STASH && !REF_IN_PAIR && DEV ? 2 : 1][STASH ? NT : 1];
+    auto stash_store = [&](const Node &n) {
+        if constexpr (STASH) {
+#pragma unroll
+            for (int p = 0; p < WORDS; ++p) s_node[p][tid] = n.w[p];
+            if constexpr (!REF_IN_PAIR && DEV) {
+                s_nref[0][tid] = n.br;
+                s_nref[1][tid] = n.bt;
+            }
+        }
+    };
+    auto stash_load = [&](Node &n) {
+        if constexpr (STASH) {
+#pragma unroll
+            for (int p = 0; p < WORDS; ++p) n.w[p] = s_node[p][tid];
+            if constexpr (!REF_IN_PAIR && DEV) {
+                n.br = s_nref[0][tid];
+                n.bt = s_nref[1][tid];
+            } else {
+                n.br = C(0);
+                n.bt = C(0);
+            }
+        }
+    };
     // State of plane zp for this thread's tile node and its halo node.
     auto load_plane = [&](int zp, Node &k, Node &h) {
         const unsigned zoff = (unsigned)zmap(zp) * plane;
@@ -1119,8 +1171,8 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         // slot `slot` at offset (dx, dy).  Plain storage keeps f* (the rest
         // part r0 closes the sum exactly: the rounded 1/3 + 6/18 + 12/36 is
         // not 1).  Deviation storage encodes K (f* - w rho_r(dest)) as
-        // A_a + K w (rho_r(own) - rho_r(dest)) with A_a = K (f* - w rho_r(own)),
-        // so that A_a carries no O(rho) part.
+        // fs_a + K w (rho - rho_r(dest)) with fs_a = K (f* - w rho), so that
+        // no term carries an O(rho) part.
         auto rref = [&](int slot, int idx) -> C {
             if constexpr (OWN_RREF) return s_rref[slot][idx];
             else return s_rho[slot][idx];
@@ -1140,22 +1192,39 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         }
         // Random bits of the stochastic rounding (FP16, BF16): a hash of the
         // node's index in the lattice and of the FP32 bits of its rho and T
-        // (which change from step to step wherever the field evolves), one
-        // draw per stored population.  A function of the node's data only,
-        // so results do not depend on the launch shape.
+        // (which change from step to step wherever the field evolves).  A
+        // function of the node's data only, so results do not depend on the
+        // launch shape.  The seed's upper half, which depends on every bit
+        // of the products, is folded into the lower one; word k = (seed ^ c_k)
+        // * m is then a bijection of the seed, so its top and bottom
+        // kSrBits-bit fields are independent draws: f_a takes the top field
+        // of word a, g_a the bottom one, and the D3Q19 populations without a
+        // temperature partner (a >= QT) share words two by two.
         unsigned sr_seed = own;
-        if constexpr (sizeof(C) == 4)
+        if constexpr (sizeof(C) == 4) {
             sr_seed = (own ^ (__builtin_bit_cast(unsigned, rho) * 0x9E3779B1u)) ^
                       (__builtin_bit_cast(unsigned, T) * 0x85EBCA77u);
-        auto srb = [&](int a) -> unsigned { return (sr_seed ^ (0x9E3779B9u * (unsigned)(a + 1))) * 0x7FEB352Du; };
-        auto fval = [&](int a, int slot, int dx, int dy) -> E {
-            if constexpr (DEV) {
-                const C bd = rref(slot, li + dy * EX + dx);
-                return ST::enc_r(fmad(C(K * w19(a)), own_rref - bd, fa[a]), srb(a));
+            sr_seed ^= sr_seed >> 16;
+        }
+        auto srw = [&](int k) -> unsigned { return (sr_seed ^ (0x9E3779B9u * (unsigned)(k + 1))) * 0x7FEB352Du; };
+        auto srr = [&](int a) -> unsigned {
+            if constexpr (HasStochasticRounding<ST>::value) {
+                constexpr int B = ST::kSrBits;
+                constexpr unsigned lo = (1u << B) - 1u;
+                if (a >= G0) return srw(a - G0) & lo;
+                if (a < QT) return srw(a) >> (32 - B);
+                const int k = QT + (a - QT) / 2;
+                return ((a - QT) & 1) ? (srw(k) & lo) : (srw(k) >> (32 - B));
             } else {
-                return ST::enc(fa[a]);
+                return 0u;
             }
         };
+        // Value stored for population a at its destination (before encoding).
+        auto fdest = [&](int a, int slot, int dx, int dy) -> C {
+            if constexpr (DEV) return fmad(C(K * w19(a)), rho - rref(slot, li + dy * EX + dx), fs[a]);
+            else return fa[a];
+        };
+        auto fval = [&](int a, int slot, int dx, int dy) -> E { return ST::enc_r(fdest(a, slot, dx, dy), srr(a)); };
         // g+ = w T_emit + gs; the deviation formats encode against the
         // destination's T_r as above.  A destination in the reservoir layer
         // receives w T_shell.  Plain storage forms the rest part as T minus
@@ -1180,7 +1249,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
                 const C bd = s_tref[slot][li + dy * EX + dx];
                 const C wK = K * wg(a);
                 if (to_shell) return wK * (P.T_shell - bd);
-                return fmad(wK, own_tref - bd, ga[a]);
+                return fmad(wK, T_emit - bd, gs[a]);
             } else {
                 if (to_shell) return wtimes(a, P.T_shell);
                 return ga[a];
@@ -1192,23 +1261,28 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
             stored = true;
             // f_a and g_a of the same velocity (a < QT) go to the same
             // neighbour and share a word of the paired layout: one store.
-            auto word = [](E lo, E hi) { return pack_pair<E>(lo, hi); };
 #pragma unroll
             for (int a = 0; a < QT; ++a) {
                 const int ex = kE19X[a], ey = kE19Y[a], ez = kE19Z[a];
                 const bool to_shell = xs[ex + 1] || ys[ey + 1] || zs[ez + 1];
                 io.store_pair(LY::pair_of(a), Yo[ey + 1] + Xo[ex + 1], Zo[ez + 1],
-                              word(fval(a, sl[ez + 1], ex, ey),
-                                   ST::enc_r(gval(a, sl[ez + 1], ex, ey, to_shell), srb(G0 + a))));
+                              ST::enc_pair_r(fdest(a, sl[ez + 1], ex, ey), srr(a),
+                                             gval(a, sl[ez + 1], ex, ey, to_shell), srr(G0 + a)));
             }
+            // The others two at a time (one conversion), stored half by half.
+            static_assert((19 - QT) % 2 == 0, "D3Q19 populations without a partner come in pairs");
 #pragma unroll
-            for (int a = QT; a < 19; ++a) {
+            for (int a = QT; a < 19; a += 2) {
                 const int ex = kE19X[a], ey = kE19Y[a], ez = kE19Z[a];
-                io.store(a, Yo[ey + 1] + Xo[ex + 1], Zo[ez + 1], fval(a, sl[ez + 1], ex, ey));
+                const int ex1 = kE19X[a + 1], ey1 = kE19Y[a + 1], ez1 = kE19Z[a + 1];
+                const PairWord<E> w = ST::enc_pair_r(fdest(a, sl[ez + 1], ex, ey), srr(a),
+                                                     fdest(a + 1, sl[ez1 + 1], ex1, ey1), srr(a + 1));
+                io.store(a, Yo[ey + 1] + Xo[ex + 1], Zo[ez + 1], pair_half<E>(w, 0));
+                io.store(a + 1, Yo[ey1 + 1] + Xo[ex1 + 1], Zo[ez1 + 1], pair_half<E>(w, 1));
             }
             if constexpr (REF_IN_PAIR) {
                 io.store_pair(LY::pair_of(LY::kPop), rowb, Zc,
-                              word(__builtin_bit_cast(E, ST::renc(rho)), __builtin_bit_cast(E, ST::renc(T))));
+                              pack_pair<E>(__builtin_bit_cast(E, ST::renc(rho)), __builtin_bit_cast(E, ST::renc(T))));
             } else if constexpr (DEV) {
                 io.store_ref(0, irow * RU, (ZOff)z * plane * RU, ST::renc(rho));
                 io.store_ref(1, irow * RU, (ZOff)z * plane * RU, ST::renc(T));
@@ -1222,11 +1296,11 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
                 const unsigned inrow = Yo[ey + 1] + Xo[ex + 1];
                 if (WALLS) {
                     if (ez < 0 && z == 0) {  // Eq. (50): halfway bounce-back into the own node
-                        io.store(opposite(a), rowb, Zc, ST::enc_r(fa[a], srb(a)));
+                        io.store(opposite(a), rowb, Zc, ST::enc_r(fa[a], srr(a)));
                         continue;
                     }
                     if (ez > 0 && z == nz - 1) {  // Eq. (50) at a top wall, or out through the open top
-                        if (P.top_wall) io.store(opposite(a), rowb, Zc, ST::enc_r(fa[a], srb(a)));
+                        if (P.top_wall) io.store(opposite(a), rowb, Zc, ST::enc_r(fa[a], srr(a)));
                         continue;
                     }
                     if (ez < 0 && z == nz - 1 && !P.top_wall)  // open top: unknown f copied from below
@@ -1245,20 +1319,20 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
                             const C Tw = bottom ? T_bottom : (C)P.T_top;
                             const C v = DEV ? fmad(K * wg(a), C(2) * Tw - T - own_tref, -gs[a])
                                             : fmad(C(2) * wg(a), Tw, -ga[a]);
-                            io.store(G0 + opposite(a), rowb, Zc, ST::enc_r(v, srb(G0 + a)));
+                            io.store(G0 + opposite(a), rowb, Zc, ST::enc_r(v, srr(G0 + a)));
                             continue;
                         }
                     }
                     const bool to_shell = xs[ex + 1] || ys[ey + 1] || zs[ez + 1];
                     io.store(G0 + a, Yo[ey + 1] + Xo[ex + 1], Zo[ez + 1],
-                             ST::enc_r(gval(a, sl[ez + 1], ex, ey, to_shell), srb(G0 + a)));
+                             ST::enc_r(gval(a, sl[ez + 1], ex, ey, to_shell), srr(G0 + a)));
                 }
             } else {
                 // temperature held fixed: g stays at the node (re-encoded against the new reference)
     #pragma unroll
                 for (int a = 0; a < QT; ++a) {
                     const C v = DEV ? fmad(K * wg(a), nd.bt - own_tref, nd.r[a]) : nd.r[a];
-                    io.store(G0 + a, rowb, Zc, ST::enc_r(v, srb(G0 + a)));
+                    io.store(G0 + a, rowb, Zc, ST::enc_r(v, srr(G0 + a)));
                 }
             }
             if constexpr (DEV) {
@@ -1332,6 +1406,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
             }
         }
         plane_moments(1, cur, h0, c_rho, c_T, c_psi);
+        stash_store(cur);
         if constexpr (DFD) {
             plane_velocity(0, z0 - 1);
             plane_velocity(1, z0);
@@ -1344,11 +1419,21 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         const unsigned zoff2 = (unsigned)zmap(z + 2) * plane;
         if (z + 2 <= zend) load_node(irow, zoff2, nq);
         __syncthreads();
-        if (active) {
-            if constexpr (VEL) velocity_out(z, s, cur, c_rho, c_psi);
-            else collide_stream(z, s, cur, c_rho, c_T, c_psi);
+        if constexpr (STASH) {
+            Node cw;
+            stash_load(cw);
+            stash_store(nxt);
+            if (active) {
+                if constexpr (VEL) velocity_out(z, s, cw, c_rho, c_psi);
+                else collide_stream(z, s, cw, c_rho, c_T, c_psi);
+            }
+        } else {
+            if (active) {
+                if constexpr (VEL) velocity_out(z, s, cur, c_rho, c_psi);
+                else collide_stream(z, s, cur, c_rho, c_T, c_psi);
+            }
+            cur = nxt;
         }
-        cur = nxt;
         nxt = nq;
         // Halo loads not issued inside a collision: inactive tile threads,
         // the velocity pass, and HALO_AT == 2.
