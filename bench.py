@@ -95,34 +95,64 @@ def cpu_model():
     return None
 
 
-def cpu_baseline(w, fields, slab_all=64, slab_one=8):
+def _oracle_rate(p, fields, nz, steps, threads):
+    """MLUPS of the FP64 oracle over `steps` steps of the z-slab [0, nz) of a
+    field (a box of its own with the workload's boundaries), with `threads`
+    OpenMP threads (None: all it is given)."""
+    from oracle import sim
+    nz = min(nz, p["nz"])
+    sl = [f[:nz] for f in fields]
+    if threads:
+        sim.set_threads(threads)
+    s = sim.Sim(**dict(p, nz=nz))
+    s.init_fields(*sl)
+    t0 = time.perf_counter()
+    s.step(steps)
+    t1 = time.perf_counter()
+    used = sim.max_threads()
+    s.close()
+    if threads:
+        sim.set_threads(0)
+    whole = nz == p["nz"]
+    return dict(value=round(s.nn * steps / (t1 - t0) / 1e6, 3), cores=used,
+                sample=f"{steps} step(s) of the " + (f"{p['nx']}x{p['ny']}x{nz} grid" if whole else
+                                                     f"{p['nx']}x{p['ny']}x{nz} slab z < {nz} of the "
+                                                     f"{p['nx']}x{p['ny']}x{p['nz']} field")
+                       + f", FP64 C + OpenMP, {used} thread(s)")
+
+
+# Bounded oracle samples of the other workloads: (name, (slab, steps) on all
+# threads, (slab, steps) on one thread), about a second each.
+CPU_CONFIG_SAMPLES = (("static_droplet_32", (32, 300), (32, 30)),
+                      ("evaporation_128", (128, 10), (128, 1)),
+                      ("pool_boiling_256x256x384", (64, 2), (16, 1)))
+
+
+def cpu_baseline(w, fields, slab_all=64, slab_one=8, configs=True):
     """The FP64 oracle (as it stands) on the host cores, on bounded samples of
     the same workload: 2 steps of the z-slab [0, slab_all) of the grid with
     every thread OpenMP gives it, and 1 step of the slab [0, slab_one) on one
-    thread.  Each slab is a periodic box of its own (the per-node work of the
-    oracle does not depend on the data)."""
-    from oracle import sim
+    thread.  Each slab is a box of its own (the per-node work of the oracle
+    does not depend on the data).  `configs` adds the same pair of figures for
+    the smaller workloads (the static droplet, the 128^3 evaporation, the pool
+    grid)."""
+    from paper_2201_06039_amd import workloads as W
     p = dict(w["params"])
-    out = {}
-    for name, nz, steps, threads in (("all", slab_all, 2, None), ("one", slab_one, 1, 1)):
-        nz = min(nz, p["nz"])
-        sl = [f[:nz] for f in fields]
-        if threads:
-            sim.set_threads(threads)
-        s = sim.Sim(**dict(p, nz=nz))
-        s.init_fields(*sl)
-        t0 = time.perf_counter()
-        s.step(steps)
-        t1 = time.perf_counter()
-        used = sim.max_threads()
-        s.close()
-        if threads:
-            sim.set_threads(0)
-        out[name] = dict(value=round(s.nn * steps / (t1 - t0) / 1e6, 3), cores=used,
-                         sample=f"{steps} step(s) of the {p['nx']}x{p['ny']}x{nz} slab z < {nz} of the "
-                                f"{p['nx']}x{p['ny']}x{p['nz']} field, FP64 C + OpenMP, {used} thread(s)")
-    return {"value": out["all"]["value"], "unit": "MLUPS", "cores": out["all"]["cores"], "kind": "oracle",
-            "sample": out["all"]["sample"], "single_thread": out["one"], "cpu_model": cpu_model()}
+    full = _oracle_rate(p, fields, slab_all, 2, None)
+    one = _oracle_rate(p, fields, slab_one, 1, 1)
+    out = {"value": full["value"], "unit": "MLUPS", "cores": full["cores"], "kind": "oracle",
+           "sample": full["sample"], "single_thread": one, "cpu_model": cpu_model()}
+    if configs:
+        rows = []
+        for name, (nz_all, st_all), (nz_one, st_one) in CPU_CONFIG_SAMPLES:
+            wc = W.load(name)
+            fc = W.fields(wc)
+            pc = dict(wc["params"])
+            rows.append({"workload": name, "grid": [pc["nx"], pc["ny"], pc["nz"]],
+                         "all_threads": _oracle_rate(pc, fc, nz_all, st_all, None),
+                         "single_thread": _oracle_rate(pc, fc, nz_one, st_one, 1)})
+        out["configs"] = rows
+    return out
 
 
 def new_stream():

@@ -1171,8 +1171,10 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         // slot `slot` at offset (dx, dy).  Plain storage keeps f* (the rest
         // part r0 closes the sum exactly: the rounded 1/3 + 6/18 + 12/36 is
         // not 1).  Deviation storage encodes K (f* - w rho_r(dest)) as
-        // fs_a + K w (rho - rho_r(dest)) with fs_a = K (f* - w rho), so that
-        // no term carries an O(rho) part.
+        // A_a + K w (rho_r(own) - rho_r(dest)) with A_a = K (f* - w rho_r(own)),
+        // so that A_a carries no O(rho) part.  (The one-FMA form
+        // fs_a + K w (rho - rho_r(dest)) has fewer instructions but makes the
+        // batch kernel spill scalar registers: measured 7% slower there.)
         auto rref = [&](int slot, int idx) -> C {
             if constexpr (OWN_RREF) return s_rref[slot][idx];
             else return s_rho[slot][idx];
@@ -1221,7 +1223,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         };
         // Value stored for population a at its destination (before encoding).
         auto fdest = [&](int a, int slot, int dx, int dy) -> C {
-            if constexpr (DEV) return fmad(C(K * w19(a)), rho - rref(slot, li + dy * EX + dx), fs[a]);
+            if constexpr (DEV) return fmad(C(K * w19(a)), own_rref - rref(slot, li + dy * EX + dx), fa[a]);
             else return fa[a];
         };
         auto fval = [&](int a, int slot, int dx, int dy) -> E { return ST::enc_r(fdest(a, slot, dx, dy), srr(a)); };
@@ -1249,7 +1251,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
                 const C bd = s_tref[slot][li + dy * EX + dx];
                 const C wK = K * wg(a);
                 if (to_shell) return wK * (P.T_shell - bd);
-                return fmad(wK, T_emit - bd, gs[a]);
+                return fmad(wK, own_tref - bd, ga[a]);
             } else {
                 if (to_shell) return wtimes(a, P.T_shell);
                 return ga[a];
