@@ -361,6 +361,7 @@ def batch_run(storage, steps, warmup, name="batch_256", launch=None):
     else:
         tuned_ms = round(b.autotune(steps=5), 5)
     launch = b.launch()
+    tiles = [b.case_tile(i) for i in range(len(cases))]
     b.step(warmup)
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record(b.stream)
@@ -372,8 +373,8 @@ def batch_run(storage, steps, warmup, name="batch_256", launch=None):
         b.reduce(i)  # raises if any lattice went unstable
     b.close()
     nodes = wb["nodes"]
-    tx, ty = launch["tile_x"], launch["tile_y"]
-    slots = sum(-(-c["params"]["nx"] // tx) * tx * -(-c["params"]["ny"] // ty) * ty * c["params"]["nz"] for c in cases)
+    slots = sum(-(-c["params"]["nx"] // tx) * -(-c["params"]["ny"] // ty) * thr * c["params"]["nz"]
+                for c, (tx, ty, thr) in zip(cases, tiles))
     return {"workload": name, "cases": len(cases), "nodes": nodes, "storage": storage,
             "value": round(nodes / ms / 1e3, 2), "unit": "MLUPS", "ms_per_step": round(ms, 5), "steps": steps,
             "roofline_frac": round(bytes_alg(storage) * nodes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),

@@ -292,15 +292,25 @@ int lbm_batch_step(lbm_batch *b, int n);
 int lbm_batch_get_rho_u_T(lbm_batch *b, int c, double *rho, double *ux, double *uy, double *uz, double *T);
 int lbm_batch_reduce(lbm_batch *b, int c, double *mass, double *energy);
 
-/* Launch shape shared by all lattices: tile (as lbm_set_launch), z-chunk
+/* Launch shape: tile (as lbm_set_launch, shared by all lattices), z-chunk
  * length (clamped to each lattice's nz) and the number of persistent
  * workgroups (0: two per compute unit's worth of resident 256-thread groups;
- * at most the number of work items is used).  EINVAL for unsupported shapes. */
+ * at most the number of work items is used).  tile_x = tile_y = 0 selects
+ * fitted tiles: 512-thread workgroups, each lattice with its own tile of
+ * 256..512 nodes (width a multiple of 4, whole x rows for lattices up to 64
+ * wide, at least 64 otherwise) chosen to leave the fewest thread slots idle
+ * on its nx x ny planes (not with FP64 storage).  Results do not depend on
+ * the launch.  EINVAL for unsupported shapes. */
 int lbm_batch_set_launch(lbm_batch *b, int tile_x, int tile_y, int chunk_z, int workgroups);
 int lbm_batch_get_launch(const lbm_batch *b, int *tile_x, int *tile_y, int *chunk_z, int *workgroups, int *items);
 
+/* The tile lattice c (0 <= c < ncases) runs with under the current launch,
+ * and the threads of its workgroups (tile_x * tile_y, or 512 with fitted
+ * tiles).  EINVAL for a bad index or NULL output. */
+int lbm_batch_case_tile(const lbm_batch *b, int c, int *tile_x, int *tile_y, int *threads);
+
 /* Autotuner: times `steps` launches of each candidate launch shape (every
- * supported tile, chunks of 8, 16, 32 and 64 planes, one and two persistent
+ * supported tile and fitted tiles, chunks of 8, 16, 32 and 64 planes, one and two persistent
  * groups per compute unit) on the current state, keeps the fastest, and
  * restores the state (the timed launches only write the idle population copy
  * and the phi_s planes, which are put back).  *best_ms receives its time per

@@ -489,6 +489,8 @@ int step_once(lbm_handle *h) {
     A.nz = h->p.nz;
     A.ntx = (h->p.nx + h->tile_x - 1) / h->tile_x;
     A.nty = (h->p.ny + h->tile_y - 1) / h->tile_y;
+    A.tile_x = h->tile_x;
+    A.tile_y = h->tile_y;
     A.cz = h->chunk_z;
     A.P = make_phys<C>(&h->p);
     A.wall = h->r_wall;
@@ -1006,10 +1008,58 @@ void drop_graphs(lbm_batch *b) {
     }
 }
 
+// tile_x = tile_y = 0 asks for fitted tiles: each lattice its own shape,
+// in 512-thread workgroups (not for FP64, whose step fits 256 threads only).
+constexpr int kFitThreads = 512;
+
 bool tile_supported(int storage, int tx, int ty) {
+    if (tx == 0 && ty == 0) return storage != LBM_STORE_F64;
     bool ok = false;
     for (const TileShape &t : kTiles) ok = ok || (t.tx == tx && t.ty == ty);
     return ok && (storage != LBM_STORE_F64 || tx * ty == 256);
+}
+
+// The fitted tile of a lattice: of the shapes 4k wide with 256..512 nodes
+// whose extended tile fits the kernel's LDS ring (kFitNodes) and that span
+// whole x rows (at least nx rounded up to 4k wide) or are at least 64 wide,
+// the one that leaves the fewest of its workgroups' 512 thread slots idle;
+// shapes within 2% of it go to the smaller halo, then to the wider tile.
+// Its tile count stays within the lattice's share of the work list.
+// Measured on the 256-lattice batch (L = 24..96): any 4k width 3.26 ms,
+// widths from 32 3.02 ms, whole rows 2.90 ms per step (32 x 16 tiles:
+// 3.41 ms) -- narrow tiles cost more in coalescing than their fit saves.
+constexpr int kFitMinWidth = 64;
+constexpr double kFitTolerance = 0.02;
+
+TileShape fitted_tile(const lbm_params &p) {
+    const size_t bound = max_workgroups(&p);
+    TileShape best{32, 16};
+    double be = -1.0;
+    int bh = 1 << 30;
+    const int nx4 = (p.nx + 3) / 4 * 4;
+    for (int tx = nx4 < kFitMinWidth ? nx4 : kFitMinWidth; tx <= 128; tx += 4) {
+        for (int ty = 2; ty <= 128; ++ty) {
+            const int nt = tx * ty;
+            if (nt > kFitThreads || nt < 256 || (tx + 2) * (ty + 2) > lbm::kFitNodes) continue;
+            const size_t tiles = (size_t)((p.nx + tx - 1) / tx) * (size_t)((p.ny + ty - 1) / ty);
+            if (tiles * (size_t)p.nz > bound) continue;
+            const double e = (double)p.nx * p.ny / ((double)tiles * kFitThreads);
+            const int halo = 2 * (tx + ty);
+            const bool better =
+                e > be + kFitTolerance || (e > be - kFitTolerance && (halo < bh || (halo == bh && tx > best.tx)));
+            if (better) {
+                best = TileShape{tx, ty};
+                be = e > be ? e : be;
+                bh = halo;
+            }
+        }
+    }
+    return best;
+}
+
+// The tile lattice c runs with under the batch's launch.
+TileShape case_tile(const lbm_batch *b, int c) {
+    return b->tile_x ? TileShape{b->tile_x, b->tile_y} : fitted_tile(b->cases[c].p);
 }
 
 // Work list and step descriptors for the current launch shape.  Lattices
@@ -1026,8 +1076,9 @@ int build_batch_tables(lbm_batch *b) {
         for (int k = 0; k < b->n; ++k) {
             const int c = b->order[k];
             const lbm_params &p = b->cases[c].p;
-            const double slots = (double)((p.nx + b->tile_x - 1) / b->tile_x * b->tile_x) *
-                                 ((p.ny + b->tile_y - 1) / b->tile_y * b->tile_y) * p.nz;
+            const TileShape t = case_tile(b, c);
+            const double slots = (double)((p.nx + t.tx - 1) / t.tx) * ((p.ny + t.ty - 1) / t.ty) *
+                                 (b->tile_x ? t.tx * t.ty : kFitThreads) * p.nz;
             int best = 0;
             for (int x = 1; x < lbm::kXcds; ++x)
                 if (load[x] < load[best]) best = x;
@@ -1057,8 +1108,11 @@ int build_batch_tables(lbm_batch *b) {
         A.nx = h->p.nx;
         A.ny = h->p.ny;
         A.nz = h->p.nz;
-        A.ntx = (h->p.nx + b->tile_x - 1) / b->tile_x;
-        A.nty = (h->p.ny + b->tile_y - 1) / b->tile_y;
+        const TileShape t = case_tile(b, c);
+        A.ntx = (h->p.nx + t.tx - 1) / t.tx;
+        A.nty = (h->p.ny + t.ty - 1) / t.ty;
+        A.tile_x = t.tx;
+        A.tile_y = t.ty;
         A.cz = b->chunk_z < h->p.nz ? b->chunk_z : h->p.nz;
         A.P = make_phys<typename ST::C>(&h->p);
         desc[c] = A;
@@ -1085,11 +1139,12 @@ int build_batch_tables(lbm_batch *b) {
 
 int default_batch_workgroups(const lbm_batch *b, int tx, int ty) {
     // Two waves per SIMD fit the step kernel's registers: 8 waves per compute unit.
-    const int per_cu = (8 * 64) / (tx * ty) > 0 ? (8 * 64) / (tx * ty) : 1;
+    const int threads = tx * ty > 0 ? tx * ty : kFitThreads;
+    const int per_cu = (8 * 64) / threads > 0 ? (8 * 64) / threads : 1;
     return b->cus * per_cu;
 }
 
-template <typename ST, int TX, int TY>
+template <typename ST, int TX, int TY, bool FIT = false>
 int launch_batch_t(lbm_batch *b, int parity, int grid) {
     lbm::BatchQueue Q;
     Q.item_case = b->d_item_case;
@@ -1100,11 +1155,11 @@ int launch_batch_t(lbm_batch *b, int parity, int grid) {
     bool buf = true;
     for (int c = 0; c < b->n; ++c) buf = buf && buffer_path(b->cases[c].L);
     if (buf)
-        hipLaunchKernelGGL((lbm::k_step_batch<ST, TX, TY, true>), dim3(grid), dim3(TX * TY), 0, b->stream, d, Q,
+        hipLaunchKernelGGL((lbm::k_step_batch<ST, TX, TY, true, FIT>), dim3(grid), dim3(TX * TY), 0, b->stream, d, Q,
                            parity);
     else
-        hipLaunchKernelGGL((lbm::k_step_batch<ST, TX, TY, false>), dim3(grid), dim3(TX * TY), 0, b->stream, d, Q,
-                           parity);
+        hipLaunchKernelGGL((lbm::k_step_batch<ST, TX, TY, false, FIT>), dim3(grid), dim3(TX * TY), 0, b->stream, d,
+                           Q, parity);
     return hip_status(hipGetLastError());
 }
 
@@ -1117,6 +1172,7 @@ int launch_batch(lbm_batch *b, int parity) {
     if (tx == 64 && ty == 4) return launch_batch_t<ST, 64, 4>(b, parity, grid);
     if (tx == 32 && ty == 8) return launch_batch_t<ST, 32, 8>(b, parity, grid);
     if constexpr (sizeof(typename ST::C) == 4) {
+        if (tx == 0 && ty == 0) return launch_batch_t<ST, 32, 16, true>(b, parity, grid);  // fitted tiles
         if (tx == 64 && ty == 8) return launch_batch_t<ST, 64, 8>(b, parity, grid);
         if (tx == 32 && ty == 16) return launch_batch_t<ST, 32, 16>(b, parity, grid);
         if (tx == 128 && ty == 4) return launch_batch_t<ST, 128, 4>(b, parity, grid);
@@ -1280,6 +1336,14 @@ int lbm_batch_set_launch(lbm_batch *b, int tile_x, int tile_y, int chunk_z, int 
     return rc;
 }
 
+int lbm_batch_case_tile(const lbm_batch *b, int c, int *tile_x, int *tile_y, int *threads) {
+    if (!b || c < 0 || c >= b->n || !tile_x || !tile_y || !threads) return LBM_EINVAL;
+    const TileShape t = case_tile(b, c);
+    *tile_x = t.tx;
+    *tile_y = t.ty;
+    *threads = b->tile_x ? t.tx * t.ty : kFitThreads;
+    return LBM_OK;
+}
 int lbm_batch_get_launch(const lbm_batch *b, int *tile_x, int *tile_y, int *chunk_z, int *workgroups, int *items) {
     if (!b || !tile_x || !tile_y || !chunk_z || !workgroups || !items) return LBM_EINVAL;
     *tile_x = b->tile_x;
@@ -1323,7 +1387,9 @@ int lbm_batch_autotune(lbm_batch *b, int steps, double *best_ms) {
     double best = 1e30;
     int bt[4] = {b->tile_x, b->tile_y, b->chunk_z, b->workgroups};
     int rc = LBM_OK;
-    for (const TileShape &t : kTiles) {
+    std::vector<TileShape> shapes(std::begin(kTiles), std::end(kTiles));
+    shapes.push_back(TileShape{0, 0});  // fitted tiles
+    for (const TileShape &t : shapes) {
         if (!tile_supported(b->storage, t.tx, t.ty)) continue;
         for (int cz : chunks) {
             for (int mult = 1; mult <= 2 && !rc; ++mult) {

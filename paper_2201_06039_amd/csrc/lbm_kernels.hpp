@@ -637,8 +637,14 @@ struct StepArgs {
     size_t unn;
     int nx, ny, nz;
     int ntx, nty, cz;               // tiles in x, y; planes per chunk
+    int tile_x, tile_y;             // the tile shape (read by kernels built for fitted tiles)
     Phys<typename ST::C> P;
 };
+
+// Fitted tiles (the batch kernel): each lattice has its own tile shape
+// tile_x x tile_y of at most the workgroup's threads, whose extended tile
+// (tile_x + 2)(tile_y + 2) fits the LDS ring of kFitNodes nodes.
+constexpr int kFitNodes = 700;
 
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
@@ -675,14 +681,22 @@ struct NodeWords {
 // nodes instead of Eq. (48).  VEL: the velocity pass that precedes such a
 // step -- the same march over the planes (rho, T, psi and the LDS ring), but
 // each tile node only writes u(t) of Eq. (10) to A.uout.
-template <typename ST, int TX, int TY, bool WALLS, bool BUF, bool DFD = false, bool VEL = false>
+// FIT: the tile is A.tile_x x A.tile_y (at most TX * TY nodes, the
+// workgroup's threads; threads beyond the tile only help with the halo),
+// instead of TX x TY.
+template <typename ST, int TX, int TY, bool WALLS, bool BUF, bool DFD = false, bool VEL = false, bool FIT = false>
 __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, int slot) {
     using E = typename ST::T;  // stored element
     using C = typename ST::C;
     constexpr bool DEV = ST::kDev;
     constexpr C K = ST::kScale, IK = C(1) / ST::kScale;
-    constexpr int NT = TX * TY, EX = TX + 2, EY = TY + 2, NE = EX * EY, NH = NE - NT;
-    static_assert(NH <= NT, "halo must not exceed the tile");
+    constexpr int NT = TX * TY;  // threads of the workgroup
+    static_assert(FIT || (TX + 2) * (TY + 2) - NT <= NT, "halo must not exceed the tile");
+    // LDS nodes of a plane of the ring (the tile and its halo)
+    constexpr int NE = FIT ? kFitNodes : (TX + 2) * (TY + 2);
+    static_assert(!FIT || NE - 256 <= NT, "fitted tiles keep at least 256 nodes, so their halo fits the threads");
+    const int tile_x = FIT ? A.tile_x : TX, tile_y = FIT ? A.tile_y : TY;
+    const int EX = tile_x + 2, NTL = tile_x * tile_y, NH = EX * (tile_y + 2) - NTL;
     constexpr int QT = ST::kQT;  // velocities of the temperature lattice
     using LY = PopLayout<QT>;
     constexpr bool PAIR = paired_layout<E>();
@@ -737,13 +751,15 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     const int rest = logical / A.ntx;
     const int ity = rest % A.nty;
     const int izc = rest / A.nty;
-    const int x0 = itx * TX, y0 = ity * TY, z0 = izc * A.cz;
+    const int x0 = itx * tile_x, y0 = ity * tile_y, z0 = izc * A.cz;
     const int zend = min(z0 + A.cz, nz);
 
     const int tid = threadIdx.x;
-    const int tx = tid % TX, ty = tid / TX;
+    const int tx = tid % tile_x, ty = tid / tile_x;
     const int x = x0 + tx, y = y0 + ty;
-    const bool active = x < nx && y < ny;
+    // in_tile: the thread owns a tile node (all threads unless FIT)
+    const bool in_tile = !FIT || tid < NTL;
+    const bool active = in_tile && x < nx && y < ny;
     const int xw = x % nx, yw = y % ny;
     const int li = (ty + 1) * EX + (tx + 1);
     const unsigned irow = (unsigned)yw * nx + xw;
@@ -756,9 +772,9 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     if (has_halo) {
         int ex, ey;
         if (tid < EX) { ex = tid - 1; ey = -1; }
-        else if (tid < 2 * EX) { ex = tid - EX - 1; ey = TY; }
-        else if (tid < 2 * EX + TY) { ex = -1; ey = tid - 2 * EX; }
-        else { ex = TX; ey = tid - 2 * EX - TY; }
+        else if (tid < 2 * EX) { ex = tid - EX - 1; ey = tile_y; }
+        else if (tid < 2 * EX + tile_y) { ex = -1; ey = tid - 2 * EX; }
+        else { ex = tile_x; ey = tid - 2 * EX - tile_y; }
         const int hx = ((x0 + ex) % nx + nx) % nx;
         const int hy = ((y0 + ey) % ny + ny) % ny;
         hrow = (unsigned)hy * nx + hx;
@@ -868,7 +884,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     // State of plane zp for this thread's tile node and its halo node.
     auto load_plane = [&](int zp, Node &k, Node &h) {
         const unsigned zoff = (unsigned)zmap(zp) * plane;
-        load_node(irow, zoff, k);
+        if (in_tile) load_node(irow, zoff, k);
         if (has_halo) load_node(hrow, zoff, h);
     };
 
@@ -890,26 +906,30 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         const size_t zoff = (size_t)zmap(zp) * plane;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            s_u[slot][c][li] = A.ustage[c * A.unn + zoff + irow];
+            if (in_tile) s_u[slot][c][li] = A.ustage[c * A.unn + zoff + irow];
             if (has_halo) s_u[slot][c][hli] = A.ustage[c * A.unn + zoff + hrow];
         }
     };
     auto plane_moments = [&](int slot, const Node &kraw, const Node &hraw, C &krho, C &kT, C &kpsi) {
-        const Pops k = decode(kraw);
-        const C rho = node_rho(k), T = node_T(k);
-        const C p2 = psi_squared(P, rho, T);
-        // Unstable node (rho <= 0, psi^2 < 0 or NaN): one flag update per wave.
-        const bool bad = active && (!(rho > C(0)) || !(p2 >= C(0)));
+        bool bad = false;
+        krho = kT = kpsi = C(0);
+        if (in_tile) {
+            const Pops k = decode(kraw);
+            const C rho = node_rho(k), T = node_T(k);
+            const C p2 = psi_squared(P, rho, T);
+            // Unstable node (rho <= 0, psi^2 < 0 or NaN): one flag update per wave.
+            bad = active && (!(rho > C(0)) || !(p2 >= C(0)));
+            const C psi = Num<C>::sqrt(p2 > C(0) ? p2 : C(0));
+            s_psi[slot][li] = psi;
+            s_rho[slot][li] = rho;
+            if constexpr (OWN_RREF) s_rref[slot][li] = ST::rdec(ST::renc(rho));
+            if constexpr (DEV) s_tref[slot][li] = ST::rdec(ST::renc(T));
+            krho = rho;
+            kT = T;
+            kpsi = psi;
+        }
         const unsigned long long badmask = __ballot(bad);
         if (badmask && __lane_id() == (unsigned)(__ffsll(badmask) - 1)) atomicOr(A.status, 1u);
-        const C psi = Num<C>::sqrt(p2 > C(0) ? p2 : C(0));
-        s_psi[slot][li] = psi;
-        s_rho[slot][li] = rho;
-        if constexpr (OWN_RREF) s_rref[slot][li] = ST::rdec(ST::renc(rho));
-        if constexpr (DEV) s_tref[slot][li] = ST::rdec(ST::renc(T));
-        krho = rho;
-        kT = T;
-        kpsi = psi;
         if (has_halo) {
             const Pops h = decode(hraw);
             const C hr = node_rho(h), hT = node_T(h);
@@ -1400,8 +1420,10 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
             // The solid layer below z = 0 holds the virtual density and its
             // psi (k_wall_density) instead of a copy of the layer above.
             const unsigned nxy = plane;
-            s_rho[0][li] = (C)A.wall[irow];
-            s_psi[0][li] = (C)A.wall[nxy + irow];
+            if (in_tile) {
+                s_rho[0][li] = (C)A.wall[irow];
+                s_psi[0][li] = (C)A.wall[nxy + irow];
+            }
             if (has_halo) {
                 s_rho[0][hli] = (C)A.wall[hrow];
                 s_psi[0][hli] = (C)A.wall[nxy + hrow];
@@ -1419,7 +1441,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         plane_moments((s + 1) & 3, nxt, nxh, n_rho, n_T, n_psi);
         if constexpr (DFD) plane_velocity((s + 1) & 3, z + 1);
         const unsigned zoff2 = (unsigned)zmap(z + 2) * plane;
-        if (z + 2 <= zend) load_node(irow, zoff2, nq);
+        if (z + 2 <= zend && in_tile) load_node(irow, zoff2, nq);
         __syncthreads();
         if constexpr (STASH) {
             Node cw;
@@ -1494,7 +1516,7 @@ struct BatchQueue {
 // tiles of a lattice -- which share halo rows and the cache lines at tile
 // edges -- meet in one L2; it then helps with the other ranges.  parity = 1
 // swaps the two population copies of every lattice.
-template <typename ST, int TX, int TY, bool BUF>
+template <typename ST, int TX, int TY, bool BUF, bool FIT = false>
 __global__ void __launch_bounds__(TX *TY) k_step_batch(const StepArgs<ST> *__restrict__ cases, BatchQueue Q,
                                                        int parity) {
     __shared__ unsigned s_item;
@@ -1516,7 +1538,7 @@ __global__ void __launch_bounds__(TX *TY) k_step_batch(const StepArgs<ST> *__res
                 A.pop_in = A.pop_out;
                 A.pop_out = t;
             }
-            step_tile<ST, TX, TY, false, BUF>(A, (int)(item - Q.first_item[c]), 0);
+            step_tile<ST, TX, TY, false, BUF, false, false, FIT>(A, (int)(item - Q.first_item[c]), 0);
         }
     }
     if (threadIdx.x == 0) {

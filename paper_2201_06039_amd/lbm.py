@@ -49,7 +49,7 @@ EXPORTS = ("lbm_arena_bytes", "lbm_create", "lbm_init_fields", "lbm_step", "lbm_
            "lbm_launches_per_step", "lbm_destroy", "lbm_strerror",
            "lbm_batch_arena_bytes", "lbm_batch_create", "lbm_batch_init_case", "lbm_batch_step",
            "lbm_batch_get_rho_u_T", "lbm_batch_reduce", "lbm_batch_set_launch", "lbm_batch_get_launch",
-           "lbm_batch_autotune", "lbm_batch_destroy", "lbm_copy_probe")
+           "lbm_batch_case_tile", "lbm_batch_autotune", "lbm_batch_destroy", "lbm_copy_probe")
 
 _lib = None
 
@@ -98,6 +98,7 @@ def load_library():
     L.lbm_batch_reduce.argtypes = [vp, ctypes.c_int, dp, dp]
     L.lbm_batch_set_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.lbm_batch_get_launch.argtypes = [vp, ip, ip, ip, ip, ip]
+    L.lbm_batch_case_tile.argtypes = [vp, ctypes.c_int, ip, ip, ip]
     L.lbm_batch_autotune.argtypes = [vp, ctypes.c_int, dp]
     L.lbm_batch_destroy.argtypes = [vp]
     L.lbm_batch_destroy.restype = None
@@ -106,8 +107,8 @@ def load_library():
                  "lbm_get_state",
                  "lbm_set_state", "lbm_set_launch", "lbm_get_launch", "lbm_launches_per_step",
                  "lbm_batch_create", "lbm_batch_init_case", "lbm_batch_step", "lbm_batch_get_rho_u_T",
-                 "lbm_batch_reduce", "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_autotune",
-                 "lbm_copy_probe"):
+                 "lbm_batch_reduce", "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_case_tile",
+                 "lbm_batch_autotune", "lbm_copy_probe"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -338,6 +339,12 @@ class Batch:
         self._check("lbm_batch_get_launch", self.lib.lbm_batch_get_launch(self._h, *[ctypes.byref(x) for x in v]))
         return dict(tile_x=v[0].value, tile_y=v[1].value, chunk_z=v[2].value, workgroups=v[3].value,
                     items=v[4].value)
+
+    def case_tile(self, c):
+        """(tile_x, tile_y, threads per workgroup) of lattice c under the current launch."""
+        v = [ctypes.c_int() for _ in range(3)]
+        self._check("lbm_batch_case_tile", self.lib.lbm_batch_case_tile(self._h, int(c), *[ctypes.byref(x) for x in v]))
+        return v[0].value, v[1].value, v[2].value
 
     def autotune(self, steps=10):
         ms = ctypes.c_double()

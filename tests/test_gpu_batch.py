@@ -78,7 +78,8 @@ def test_batch_equals_solo_runs(storage):
     b.close()
 
 
-@pytest.mark.parametrize("launch", [(32, 8, 8, 0), (64, 8, 32, 7), (128, 4, 4, 1), (32, 16, 16, 1000)])
+@pytest.mark.parametrize("launch", [(32, 8, 8, 0), (64, 8, 32, 7), (128, 4, 4, 1), (32, 16, 16, 1000),
+                                    (0, 0, 16, 0), (0, 0, 64, 3)])
 def test_batch_launch_shapes(launch):
     """Tile, chunk and persistent-grid size (one workgroup included) change
     nothing in the results."""
@@ -92,6 +93,30 @@ def test_batch_launch_shapes(launch):
         for x, y in zip(b.rho_u_T(c), ref[c][0]):
             assert np.array_equal(x, y), (launch, c)
     b.close()
+
+
+def test_fitted_tiles():
+    """Fitted tiles (launch tile 0 x 0): every lattice gets its own tile of
+    256..512 nodes, 4k wide, whose extended tile fits the LDS ring of 700
+    nodes, leaving no more idle thread slots than the 32 x 16 tile; the
+    lattices still equal their solo runs bit for bit (FP32 and FP16)."""
+    import math
+    cases = small_cases()
+    for storage in ("f32", "f16"):
+        b = make_batch(cases, storage)
+        b.set_launch(0, 0, 32, 0)
+        for c, w in enumerate(cases):
+            tx, ty, thr = b.case_tile(c)
+            nx, ny = w["params"]["nx"], w["params"]["ny"]
+            assert thr == 512 and tx % 4 == 0 and 256 <= tx * ty <= 512 and (tx + 2) * (ty + 2) <= 700, (tx, ty)
+            assert math.ceil(nx / tx) * math.ceil(ny / ty) * 512 <= math.ceil(nx / 32) * math.ceil(ny / 16) * 512
+            _say(f"  {storage} lattice {c} ({nx}x{ny}): tile {tx}x{ty}")
+        ref = [solo(w, storage, [3])[0] for w in cases]
+        b.step(3)
+        for c in range(len(cases)):
+            for x, y in zip(b.rho_u_T(c), ref[c]):
+                assert np.array_equal(x, y), (storage, c)
+        b.close()
 
 
 def test_autotune_leaves_the_state_unchanged():
