@@ -135,12 +135,11 @@ size_t plane_bytes(const Layout &L, size_t k) {
 // interleave, and at 512^3 (2^27 nodes) a pad of 32832 elements measured 2%
 // (FP16) and 10% (FP32) faster than none; pads near 64 K elements measured
 // slower.  Small lattices (the batch) keep the plain stride.
-#ifndef LBM_STRIDE_PAD
-#define LBM_STRIDE_PAD 32832
-#endif
+constexpr size_t kPlanePad = 32832;
+
 size_t plane_stride(size_t nn) {
     const size_t s = align_up(nn, 128);
-    return nn >= ((size_t)1 << 22) ? s + LBM_STRIDE_PAD : s;
+    return nn >= ((size_t)1 << 22) ? s + kPlanePad : s;
 }
 
 Layout make_layout(const lbm_params *p) {
