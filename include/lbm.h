@@ -310,7 +310,7 @@ int lbm_batch_get_launch(const lbm_batch *b, int *tile_x, int *tile_y, int *chun
 int lbm_batch_case_tile(const lbm_batch *b, int c, int *tile_x, int *tile_y, int *threads);
 
 /* Autotuner: times `steps` launches of each candidate launch shape (every
- * supported tile and fitted tiles, chunks of 8, 16, 32 and 64 planes, one and two persistent
+ * supported tile and fitted tiles, chunks of 8, 16, 32, 64 and 128 planes, one and two persistent
  * groups per compute unit) on the current state, keeps the fastest, and
  * restores the state (the timed launches only write the idle population copy
  * and the phi_s planes, which are put back).  *best_ms receives its time per

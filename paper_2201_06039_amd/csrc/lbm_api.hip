@@ -1382,7 +1382,7 @@ int lbm_batch_autotune(lbm_batch *b, int steps, double *best_ms) {
         hipEventDestroy(e0);
         return LBM_EHIP;
     }
-    const int chunks[] = {8, 16, 32, 64};
+    const int chunks[] = {8, 16, 32, 64, 128};
     double best = 1e30;
     int bt[4] = {b->tile_x, b->tile_y, b->chunk_z, b->workgroups};
     int rc = LBM_OK;
