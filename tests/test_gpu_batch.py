@@ -160,6 +160,29 @@ def test_fp64_batch_against_oracle():
     b.close()
 
 
+@pytest.mark.parametrize("storage", ["f16", "bf16", "f32"])
+def test_batch_against_oracle(storage):
+    """The batch in the reduced formats against the FP64 oracle directly
+    (fitted tiles, uneven lattices of the benchmark's kinds, 30 steps): FP32
+    at the single-lattice FP32 bar for rho and T, FP16 and BF16 within one
+    rounding of the field in the storage type (2^-11, 2^-8) for rho and T and
+    20 such roundings for u in the L2 sense, as for single lattices."""
+    cases = [workload("static_droplet_32", nx=20, ny=18, nz=16, radius=5.0),
+             workload("evaporation_128", nx=24, ny=24, nz=24, radius=6.0),
+             workload("d2_law_48", nx=22, ny=20, nz=18, radius=5.0)]
+    b = make_batch(cases, storage)
+    b.set_launch(0, 0, 32, 0)
+    b.step(30)
+    tol = {"f32": 1e-5, "f16": 2.0 ** -11, "bf16": 2.0 ** -8}[storage]
+    for c, w in enumerate(cases):
+        e = errors(b.rho_u_T(c), run_oracle(w, 30))
+        _say(f"  {storage} case {c} (tile {b.case_tile(c)[:2]}): {e}")
+        assert e["rho"] <= tol and e["T"] <= tol, (c, e)
+        if storage != "f32":
+            assert e["u_l2"] <= 20 * tol, (c, e)
+    b.close()
+
+
 def test_batch_reduce_and_readout_errors():
     from paper_2201_06039_amd import lbm
     cases = small_cases()[:2]
