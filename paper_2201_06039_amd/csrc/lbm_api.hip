@@ -351,10 +351,7 @@ int hip_status(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EHIP; }
 void set_default_launch(lbm_handle *h) {
     const int nx = h->p.nx, ny = h->p.ny, nz = h->p.nz;
     const bool half = h->L.es == 2;
-    if (half && nx >= 512) {
-        h->tile_x = 128;
-        h->tile_y = 4;
-    } else if (nx >= 64) {
+    if (nx >= 64) {
         h->tile_x = 64;
         h->tile_y = 8;
     } else if (nx > 32) {

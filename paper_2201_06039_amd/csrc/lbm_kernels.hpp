@@ -719,15 +719,17 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     __shared__ C s_tref[TS][TN];  // the references every node writes for itself
     __shared__ double s_red[NT / 64];
 
-    // STASH (4-byte elements, and the batch kernel's fitted tiles): the tile
-    // node's words of plane z+1 wait in LDS from its moments until its
-    // collision (each thread reads back only its own entries, so no barrier
-    // guards them), and the words of plane z+2 load straight into the
-    // registers they left, after the barrier: no register copy of words in
-    // flight, which would wait for every load and store of the wave.
-    // Measured: FP32 512^3 7.66 -> 6.47 ms, pool grid -5%; the FP16 batch
-    // -3%; the single-lattice FP16 step at 128x4 tiles +2% (not used there).
-    constexpr bool STASH = paired_layout<E>() && (sizeof(E) == 4 || FIT);
+    // STASH: the tile node's words of plane z+1 wait in LDS from its moments
+    // until its collision (each thread reads back only its own entries, so
+    // no barrier guards them), and the words of plane z+2 load straight into
+    // the registers they left, after the barrier: no register copy of words
+    // in flight, which would wait for every load and store of the wave.
+    // Measured: FP32 512^3 7.66 -> 6.47 ms, pool grid -5%; 16-bit periodic
+    // grids with 64x8 tiles -2% (512^3, against 128x4 without) and -3%
+    // (128^3), the FP16 batch -3%; 16-bit walls +4% (not used there), and
+    // the D3Q19 temperature lattice keeps its words in registers.
+    constexpr bool STASH =
+        paired_layout<E>() && (sizeof(E) == 4 || FIT || (!WALLS && ST::kQT == 7));
     // The float constants of the model are read by vector instructions in
     // every iteration; held in scalar registers they exceed the scalar
     // register file and are spilled to vector lanes, costing one read per use.
