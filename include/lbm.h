@@ -297,9 +297,10 @@ int lbm_batch_reduce(lbm_batch *b, int c, double *mass, double *energy);
  * workgroups (0: two per compute unit's worth of resident 256-thread groups;
  * at most the number of work items is used).  tile_x = tile_y = 0 selects
  * fitted tiles: 512-thread workgroups, each lattice with its own tile of
- * 256..512 nodes (width a multiple of 4, whole x rows for lattices up to 64
- * wide, at least 64 otherwise) chosen to leave the fewest thread slots idle
- * on its nx x ny planes (not with FP64 storage).  Results do not depend on
+ * 256..512 nodes (whole x rows, exactly nx wide, for lattices up to 128
+ * wide; otherwise, or where it fits better, a multiple of 4 from 64 up to
+ * below nx) chosen to leave the fewest thread slots idle on its nx x ny
+ * planes (not with FP64 storage).  Results do not depend on
  * the launch.  EINVAL for unsupported shapes. */
 int lbm_batch_set_launch(lbm_batch *b, int tile_x, int tile_y, int chunk_z, int workgroups);
 int lbm_batch_get_launch(const lbm_batch *b, int *tile_x, int *tile_y, int *chunk_z, int *workgroups, int *items);

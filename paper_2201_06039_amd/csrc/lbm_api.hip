@@ -1015,15 +1015,17 @@ bool tile_supported(int storage, int tx, int ty) {
     return ok && (storage != LBM_STORE_F64 || tx * ty == 256);
 }
 
-// The fitted tile of a lattice: of the shapes 4k wide with 256..512 nodes
-// whose extended tile fits the kernel's LDS ring (kFitNodes) and that span
-// whole x rows (at least nx rounded up to 4k wide) or are at least 64 wide,
-// the one that leaves the fewest of its workgroups' 512 thread slots idle;
-// shapes within 2% of it go to the smaller halo, then to the wider tile.
+// The fitted tile of a lattice: of the shapes with 256..512 nodes whose
+// extended tile fits the kernel's LDS ring (kFitNodes) and that span whole x
+// rows (exactly nx wide) or are 4k wide with 64 <= width < nx, the one that
+// leaves the fewest of its workgroups' 512 thread slots idle; shapes within
+// 2% of it go to the smaller halo (the two halo rows only for whole-row
+// tiles, whose x neighbours are their own columns), then to the wider tile.
 // Its tile count stays within the lattice's share of the work list.
 // Measured on the 256-lattice batch (L = 24..96): any 4k width 3.26 ms,
-// widths from 32 3.02 ms, whole rows 2.90 ms per step (32 x 16 tiles:
-// 3.41 ms) -- narrow tiles cost more in coalescing than their fit saves.
+// widths from 32 3.02 ms, whole rows rounded up to 4k 2.90 ms per step
+// (32 x 16 tiles: 3.41 ms) -- narrow tiles cost more in coalescing than
+// their fit saves.
 constexpr int kFitMinWidth = 64;
 constexpr double kFitTolerance = 0.02;
 
@@ -1032,15 +1034,17 @@ TileShape fitted_tile(const lbm_params &p) {
     TileShape best{32, 16};
     double be = -1.0;
     int bh = 1 << 30;
-    const int nx4 = (p.nx + 3) / 4 * 4;
-    for (int tx = nx4 < kFitMinWidth ? nx4 : kFitMinWidth; tx <= 128; tx += 4) {
-        for (int ty = 2; ty <= 128; ++ty) {
+    std::vector<int> widths;
+    if (p.nx >= 2 && p.nx <= 128) widths.push_back(p.nx);
+    for (int tx = kFitMinWidth; tx <= 128 && tx < p.nx; tx += 4) widths.push_back(tx);
+    for (int tx : widths) {
+        for (int ty = 1; ty <= 256; ++ty) {
             const int nt = tx * ty;
             if (nt > kFitThreads || nt < 256 || (tx + 2) * (ty + 2) > lbm::kFitNodes) continue;
             const size_t tiles = (size_t)((p.nx + tx - 1) / tx) * (size_t)((p.ny + ty - 1) / ty);
             if (tiles * (size_t)p.nz > bound) continue;
             const double e = (double)p.nx * p.ny / ((double)tiles * kFitThreads);
-            const int halo = 2 * (tx + ty);
+            const int halo = tx == p.nx ? 2 * tx : 2 * (tx + ty) + 4;
             const bool better =
                 e > be + kFitTolerance || (e > be - kFitTolerance && (halo < bh || (halo == bh && tx > best.tx)));
             if (better) {

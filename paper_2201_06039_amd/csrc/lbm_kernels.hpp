@@ -683,7 +683,11 @@ struct NodeWords {
 // each tile node only writes u(t) of Eq. (10) to A.uout.
 // FIT: the tile is A.tile_x x A.tile_y (at most TX * TY nodes, the
 // workgroup's threads; threads beyond the tile only help with the halo),
-// instead of TX x TY.
+// instead of TX x TY.  A fitted tile exactly as wide as the lattice spans
+// whole x rows: the columns left and right of it are its own last and first
+// columns (periodic in x), so its halo is only the rows below and above it,
+// and a node of its first or last column also writes its LDS entries into
+// the opposite halo column.
 template <typename ST, int TX, int TY, bool WALLS, bool BUF, bool DFD = false, bool VEL = false, bool FIT = false>
 __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, int slot) {
     using E = typename ST::T;  // stored element
@@ -695,8 +699,11 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     // LDS nodes of a plane of the ring (the tile and its halo)
     constexpr int NE = FIT ? kFitNodes : (TX + 2) * (TY + 2);
     static_assert(!FIT || NE - 256 <= NT, "fitted tiles keep at least 256 nodes, so their halo fits the threads");
+    static_assert(!FIT || (!WALLS && !DFD && !VEL), "fitted tiles are built for the periodic batch step");
     const int tile_x = FIT ? A.tile_x : TX, tile_y = FIT ? A.tile_y : TY;
-    const int EX = tile_x + 2, NTL = tile_x * tile_y, NH = EX * (tile_y + 2) - NTL;
+    const bool wrapx = FIT && tile_x == A.nx && A.nx >= 2;  // a whole-row fitted tile
+    const int EX = tile_x + 2, NTL = tile_x * tile_y;
+    const int NH = wrapx ? 2 * tile_x : EX * (tile_y + 2) - NTL;
     constexpr int QT = ST::kQT;  // velocities of the temperature lattice
     using LY = PopLayout<QT>;
     constexpr bool PAIR = paired_layout<E>();
@@ -768,15 +775,24 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     const int xw = x % nx, yw = y % ny;
     const int li = (ty + 1) * EX + (tx + 1);
     const unsigned irow = (unsigned)yw * nx + xw;
+    // Whole-row tile: offset of the second LDS entry of a first- or last-column node.
+    auto wrap_copy = [&](int ex) -> int {
+        return !wrapx ? 0 : (ex == 0 ? tile_x : (ex == tile_x - 1 ? -tile_x : 0));
+    };
+    const int ldup = wrap_copy(tx);
 
     // Halo position owned by this thread (tid < NH): the rows below and above
-    // the tile, then the columns left and right of it.
+    // the tile, then (not for whole-row tiles) the columns left and right of it.
     const bool has_halo = tid < NH;
     unsigned hrow = 0;
-    int hli = 0;
+    int hli = 0, hdup = 0;
     if (has_halo) {
         int ex, ey;
-        if (tid < EX) { ex = tid - 1; ey = -1; }
+        if (wrapx) {
+            ey = tid < tile_x ? -1 : tile_y;
+            ex = tid < tile_x ? tid : tid - tile_x;
+        }
+        else if (tid < EX) { ex = tid - 1; ey = -1; }
         else if (tid < 2 * EX) { ex = tid - EX - 1; ey = tile_y; }
         else if (tid < 2 * EX + tile_y) { ex = -1; ey = tid - 2 * EX; }
         else { ex = tile_x; ey = tid - 2 * EX - tile_y; }
@@ -784,6 +800,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
         const int hy = ((y0 + ey) % ny + ny) % ny;
         hrow = (unsigned)hy * nx + hx;
         hli = (ey + 1) * EX + (ex + 1);
+        hdup = wrap_copy(ex);
     }
 
     auto zmap = [&](int zp) -> int {
@@ -915,6 +932,13 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
             if (has_halo) s_u[slot][c][hli] = A.ustage[c * A.unn + zoff + hrow];
         }
     };
+    // One node's entries of LDS ring slot `slot`.
+    auto ring_put = [&](int slot, int i, C psi, C rho, C T) {
+        s_psi[slot][i] = psi;
+        s_rho[slot][i] = rho;
+        if constexpr (OWN_RREF) s_rref[slot][i] = ST::rdec(ST::renc(rho));
+        if constexpr (DEV) s_tref[slot][i] = ST::rdec(ST::renc(T));
+    };
     auto plane_moments = [&](int slot, const Node &kraw, const Node &hraw, C &krho, C &kT, C &kpsi) {
         bool bad = false;
         krho = kT = kpsi = C(0);
@@ -925,10 +949,8 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
             // Unstable node (rho <= 0, psi^2 < 0 or NaN): one flag update per wave.
             bad = active && (!(rho > C(0)) || !(p2 >= C(0)));
             const C psi = Num<C>::sqrt(p2 > C(0) ? p2 : C(0));
-            s_psi[slot][li] = psi;
-            s_rho[slot][li] = rho;
-            if constexpr (OWN_RREF) s_rref[slot][li] = ST::rdec(ST::renc(rho));
-            if constexpr (DEV) s_tref[slot][li] = ST::rdec(ST::renc(T));
+            ring_put(slot, li, psi, rho, T);
+            if (FIT && ldup) ring_put(slot, li + ldup, psi, rho, T);
             krho = rho;
             kT = T;
             kpsi = psi;
@@ -939,10 +961,9 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
             const Pops h = decode(hraw);
             const C hr = node_rho(h), hT = node_T(h);
             const C hp2 = psi_squared(P, hr, hT);
-            s_psi[slot][hli] = Num<C>::sqrt(hp2 > C(0) ? hp2 : C(0));
-            s_rho[slot][hli] = hr;
-            if constexpr (OWN_RREF) s_rref[slot][hli] = ST::rdec(ST::renc(hr));
-            if constexpr (DEV) s_tref[slot][hli] = ST::rdec(ST::renc(hT));
+            const C hpsi = Num<C>::sqrt(hp2 > C(0) ? hp2 : C(0));
+            ring_put(slot, hli, hpsi, hr, hT);
+            if (FIT && hdup) ring_put(slot, hli + hdup, hpsi, hr, hT);
         }
     };
 

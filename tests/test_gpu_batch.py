@@ -97,18 +97,28 @@ def test_batch_launch_shapes(launch):
 
 def test_fitted_tiles():
     """Fitted tiles (launch tile 0 x 0): every lattice gets its own tile of
-    256..512 nodes, 4k wide, whose extended tile fits the LDS ring of 700
-    nodes, leaving no more idle thread slots than the 32 x 16 tile; the
-    lattices still equal their solo runs bit for bit (FP32 and FP16)."""
+    256..512 nodes, exactly as wide as the lattice (whole rows, whose x halo
+    comes from the tile's own columns) or 4k wide, whose extended tile fits
+    the LDS ring of 700 nodes, leaving no more idle thread slots than the
+    32 x 16 tile; the lattices still equal their solo runs bit for bit (FP32
+    and FP16).  The cases cover whole rows of odd and even width, and a
+    lattice wider than 128 with 4k-wide tiles ragged in x and y."""
     import math
     cases = small_cases()
+    evap = W.load("evaporation_128")
+    for k, (nx, ny, nz) in enumerate(((85, 20, 12), (150, 9, 10))):
+        w = copy.deepcopy(evap)
+        w["params"].update(nx=nx, ny=ny, nz=nz)
+        w["init"].update(radius=3.0, center=[nx / 3, ny / 2, nz / 2], seed=40 + k)
+        cases.append(w)
     for storage in ("f32", "f16"):
         b = make_batch(cases, storage)
         b.set_launch(0, 0, 32, 0)
         for c, w in enumerate(cases):
             tx, ty, thr = b.case_tile(c)
             nx, ny = w["params"]["nx"], w["params"]["ny"]
-            assert thr == 512 and tx % 4 == 0 and 256 <= tx * ty <= 512 and (tx + 2) * (ty + 2) <= 700, (tx, ty)
+            assert thr == 512 and (tx == nx or tx % 4 == 0) and 256 <= tx * ty <= 512, (tx, ty)
+            assert (tx + 2) * (ty + 2) <= 700, (tx, ty)
             assert math.ceil(nx / tx) * math.ceil(ny / ty) * 512 <= math.ceil(nx / 32) * math.ceil(ny / 16) * 512
             _say(f"  {storage} lattice {c} ({nx}x{ny}): tile {tx}x{ty}")
         ref = [solo(w, storage, [3])[0] for w in cases]
