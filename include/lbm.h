@@ -230,7 +230,8 @@ int lbm_get_state(lbm_handle *h, void *host_buf, size_t bytes);
 int lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes);
 
 /* Launch shape of the fused step kernel: an x-y tile of tile_x * tile_y
- * nodes per workgroup marching over chunk_z planes.  Supported tiles:
+ * nodes per workgroup marching over chunk_z planes (each thread updates one
+ * node per plane, chunk_z nodes in all).  Supported tiles:
  * 64x4, 32x8, 64x8, 32x16, 128x4 (F64 storage: 64x4 and 32x8 only);
  * chunk_z >= 1 (values above nz are clamped to nz).  EINVAL otherwise.
  * The result of a step does not depend on the launch shape. */
@@ -311,7 +312,8 @@ int lbm_batch_get_launch(const lbm_batch *b, int *tile_x, int *tile_y, int *chun
 int lbm_batch_case_tile(const lbm_batch *b, int c, int *tile_x, int *tile_y, int *threads);
 
 /* Autotuner: times `steps` launches of each candidate launch shape (every
- * supported tile and fitted tiles, chunks of 8, 16, 32, 64 and 128 planes, one and two persistent
+ * supported tile and fitted tiles, chunks of 8, 16, 32, 64 and 128 planes --
+ * the nodes each thread updates --, one and two persistent
  * groups per compute unit) on the current state, keeps the fastest, and
  * restores the state (the timed launches only write the idle population copy
  * and the phi_s planes, which are put back).  *best_ms receives its time per
