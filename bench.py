@@ -344,6 +344,68 @@ def nucleation_study(lbm, W, name="nucleation_200x200x280", gravities=(1e-5, 1.5
     return out
 
 
+def ccr_evaporation(lbm, W, name="ccr_evaporation_200x200x100", storage="f32", settle=10000, max_steps=600000,
+                    every=5000, stop_fraction=0.25):
+    """Sec. IV B: the hemisphere on the heated wall.  The first `settle` steps
+    hold the temperature lattice (thermal = 0); the state then continues with
+    it (checkpoint into a lattice with thermal = 1).  Every `every` steps:
+    the droplet mass (sum of rho over the liquid nodes, rho above the mid
+    density), the footprint diameter D = 2 (A/pi)^(1/2) of the liquid nodes of
+    the first layer, the apex height h (liquid nodes of the centre column,
+    the wall plane at z = -1/2) and the spherical-cap contact angle
+    2 atan(2h/D).  Stops when the mass falls below `stop_fraction` of its
+    value when heating starts."""
+    import numpy as np
+    w = W.load(name)
+    p = dict(w["params"])
+    mid = 0.5 * (w["init"]["rho_l"] + w["init"]["rho_g"])
+    cx, cy = (p["nx"] - 1) // 2, (p["ny"] - 1) // 2
+    t0 = time.perf_counter()
+    lat = lbm.Lattice(dict(p, thermal=0), storage=storage, device="cuda:0", stream=new_stream())
+    lat.init_fields(*W.fields(w))
+    lat.step(settle)
+    blob = lat.get_state()
+    lat.close()
+    lat = lbm.Lattice(p, storage=storage, device="cuda:0", stream=new_stream())
+    lat.set_state(blob)
+
+    def sample(t):
+        rho = lat.rho_u_T()[0]
+        liq = rho > mid
+        area = float(liq[0].sum())
+        D = 2.0 * (area / np.pi) ** 0.5
+        h = float(liq[:, cy:cy + 2, cx:cx + 2].sum(axis=0).max())
+        theta = float(np.degrees(2.0 * np.arctan2(2.0 * h, D))) if D > 0 else 0.0
+        return dict(t=t, mass=float(rho[liq].sum()), D=round(D, 2), h=h, theta=round(theta, 1))
+
+    samples = [sample(0)]
+    m0 = samples[0]["mass"]
+    t = 0
+    while t < max_steps and samples[-1]["mass"] > stop_fraction * m0:
+        lat.step(every)
+        t += every
+        samples.append(sample(t))
+        q = samples[-1]
+        print(f"# ccr {storage} t={t}: mass {q['mass'] / m0:.4f} D {q['D']} h {q['h']} theta {q['theta']}",
+              file=sys.stderr, flush=True)
+    lat.close()
+    for s in samples:
+        s["mass"] = round(s["mass"] / m0, 4)
+    D0 = samples[0]["D"]
+    pinned = [s for s in samples if abs(s["D"] - D0) <= 2.0]
+    last_pinned = max((k for k, s in enumerate(samples) if all(abs(q["D"] - D0) <= 2.0 for q in samples[:k + 1])),
+                      default=0)
+    out = {"workload": name, "storage": storage, "settle_steps": settle, "readout_every": every,
+           "D_at_heating": D0, "theta_at_heating": samples[0]["theta"],
+           "ccr_until_step": samples[last_pinned]["t"], "mass_at_ccr_end": samples[last_pinned]["mass"],
+           "theta_at_ccr_end": samples[last_pinned]["theta"], "samples_with_D_within_2": len(pinned),
+           "samples": samples, "wall_s": round(time.perf_counter() - t0, 1)}
+    print(f"# ccr {name} {storage}: D {D0} theta {samples[0]['theta']} -> CCR until t = {out['ccr_until_step']} "
+          f"(mass {out['mass_at_ccr_end']}, theta {out['theta_at_ccr_end']}); {len(samples)} readouts",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def batch_run(storage, steps, warmup, name="batch_256", launch=None):
     """The batched step over the lattices of workload `name`: autotune the
     launch on the initial state (or take `launch` = (tile_x, tile_y, chunk_z,
@@ -477,6 +539,9 @@ def main():
     ap.add_argument("--nucleation", action="store_true",
                     help="only run the bubble nucleation and departure test of Sec. IV C at five gravities "
                          "(about 3 minutes) and print its JSON")
+    ap.add_argument("--ccr", action="store_true",
+                    help="only run the evaporation of a pinned droplet on the heated wall of Sec. IV B (FP64, FP32 "
+                         "and FP16 storage, about 9 minutes) and print its JSON")
     ap.add_argument("--workloads", default="evaporation_128,pool_boiling_256x256x384",
                     help="comma-separated workloads timed in the other-workload leg")
     ap.add_argument("--divu", default="local", choices=["local", "fd"],
@@ -504,6 +569,15 @@ def main():
 
     if args.nucleation:
         print(json.dumps(nucleation_study(lbm, W)), flush=True)
+        return
+
+    if args.ccr:
+        runs = [ccr_evaporation(lbm, W, storage=st) for st in ("f64", "f32", "f16")]
+        ref = {s["t"]: s for s in runs[0]["samples"]}
+        for r in runs[1:]:
+            common = [s for s in r["samples"] if s["t"] in ref]
+            r["vs_f64"] = {k: round(max(abs(s[k] - ref[s["t"]][k]) for s in common), 4) for k in ("mass", "D", "theta")}
+        print(json.dumps({"ccr_evaporation": runs}), flush=True)
         return
 
     if args.batch_only:

@@ -66,9 +66,11 @@ extern "C" {
  * solid node carries rho_w = phi rho_ave - drho, rho_ave the weighted mean of
  * its five fluid neighbours (weights 1/18 and 1/36 of Eq. (5)), and psi of
  * Eq. (8) at rho_w and the temperature of the fluid node above it; phi =
- * wet_phi_in, drho = wet_drho inside a square of side wet_square centred at
- * ((nx-1)/2, (ny-1)/2) (Sec. IV C's patterned wall), phi = wet_phi, drho = 0
- * elsewhere.  phi > 1 wets (contact angle below 90 degrees), phi < 1 or
+ * wet_phi_in, drho = wet_drho inside the patch -- a square of side
+ * wet_square centred at ((nx-1)/2, (ny-1)/2) (Sec. IV C's patterned wall)
+ * and a disc of diameter wet_disc centred there (a contact line pinned on
+ * its rim stands in for Sec. IV B's hysteresis window), either or both;
+ * membership decided in FP64 -- phi = wet_phi, drho = 0 elsewhere.  phi > 1 wets (contact angle below 90 degrees), phi < 1 or
  * drho > 0 does not.  Adds one launch per step. */
 #define LBM_WET_NEUTRAL 0
 #define LBM_WET_VIRTUAL_DENSITY 1
@@ -160,6 +162,7 @@ typedef struct lbm_params {
     double wet_phi_in;       /* > 0: phi inside the square                     */
     double wet_drho;         /* >= 0: drho inside the square                   */
     double wet_square;       /* >= 0: side of the centred square (0: none)     */
+    double wet_disc;         /* >= 0: diameter of the centred disc (0: none)   */
 } lbm_params;
 
 typedef struct lbm_handle lbm_handle;

@@ -79,10 +79,11 @@ typedef struct orc_params {
     int wet_mode;          /* bottom wall wettability: 0 neutral (the solid node mirrors the fluid
                               node above it); 1 virtual density rho_w = phi rho_ave - drho, after
                               Li, Luo, Kang & Chen (Phys. Rev. E 90, 053301, 2014) */
-    double wet_phi;        /* wet_mode 1, outside the square: rho_w = wet_phi * rho_ave */
-    double wet_phi_in;     /* wet_mode 1, inside the square: rho_w = wet_phi_in * rho_ave - wet_drho */
+    double wet_phi;        /* wet_mode 1, outside the patch: rho_w = wet_phi * rho_ave */
+    double wet_phi_in;     /* wet_mode 1, inside the patch: rho_w = wet_phi_in * rho_ave - wet_drho */
     double wet_drho;
-    double wet_square;     /* side of the square centred at ((nx-1)/2, (ny-1)/2); 0: none */
+    double wet_square;     /* patch: the square of this side centred at ((nx-1)/2, (ny-1)/2); 0: none */
+    double wet_disc;       /* patch: the disc of this diameter centred there; 0: none */
 } orc_params;
 
 typedef struct orc_sim {
@@ -364,10 +365,14 @@ static double bottom_wall_temperature(const orc_params *p, int x, int y) {
  * Whole-grid passes.
  * ------------------------------------------------------------------------- */
 
-/* Whether bottom-wall node (x, y) lies in the centred square. */
-static int in_wet_square(const orc_params *p, int x, int y) {
+/* Whether bottom-wall node (x, y) lies in the wettability patch: the centred
+ * square or the centred disc. */
+static int in_wet_patch(const orc_params *p, int x, int y) {
     const double cx = 0.5 * (p->nx - 1), cy = 0.5 * (p->ny - 1), h = 0.5 * p->wet_square;
-    return p->wet_square > 0.0 && fabs(x - cx) <= h && fabs(y - cy) <= h;
+    const double dx = x - cx, dy = y - cy, r = 0.5 * p->wet_disc;
+    const int in_square = p->wet_square > 0.0 && fabs(dx) <= h && fabs(dy) <= h;
+    const int in_disc = p->wet_disc > 0.0 && dx * dx + dy * dy <= r * r;
+    return in_square || in_disc;
 }
 
 /* Wettability of the bottom wall (Sec. IV B-C; the paper takes its scheme
@@ -400,7 +405,7 @@ static void pass_wall_density(orc_sim *s) {
                 den += w;
             }
             const double rho_ave = num / den;
-            const double rw = in_wet_square(p, x, y) ? p->wet_phi_in * rho_ave - p->wet_drho : p->wet_phi * rho_ave;
+            const double rw = in_wet_patch(p, x, y) ? p->wet_phi_in * rho_ave - p->wet_drho : p->wet_phi * rho_ave;
             const double p2 = psi_squared(p, s->Tc, rw, s->T[node_index(p, x, y, 0)]);
             if (!(rw > 0.0) || !(p2 >= 0.0)) bad = 1;
             s->rho_w[(long)y * p->nx + x] = rw;
@@ -727,7 +732,7 @@ int orc_create(const orc_params *p, orc_sim **out) {
     if (p->bc_z < 0 || p->bc_z > 2) return ORC_EINVAL;
     if (p->bc_z != 0 && p->nz < 3) return ORC_EINVAL;
     if (p->wet_mode != 0 && (p->wet_mode != 1 || p->bc_z == 0 || !(p->wet_phi > 0.0) || !(p->wet_phi_in > 0.0) ||
-                             !(p->wet_drho >= 0.0) || !(p->wet_square >= 0.0)))
+                             !(p->wet_drho >= 0.0) || !(p->wet_square >= 0.0) || !(p->wet_disc >= 0.0)))
         return ORC_EINVAL;
     if (p->bc_T_shell && (p->bc_z != 0 || !p->thermal || !(p->T_shell > 0.0))) return ORC_EINVAL;
     if (p->thermal_bgk != 0 && p->thermal_bgk != 1) return ORC_EINVAL;

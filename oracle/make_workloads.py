@@ -97,6 +97,26 @@ def wetting_phi(theta, sigma, lo, hi):
     return round(phi, 3)
 
 
+def droplet_vapour(radius, sigma, a=A_IVA, frac=0.86, n=80, steps=3000, guess=0.455):
+    """Vapour density in equilibrium with a droplet of the given radius in this
+    model (isothermal at frac T_c), from the oracle: a sphere of that radius in
+    an n^3 periodic box, the vapour started at `guess`; the mean density of
+    the nodes more than radius + 8 from the centre after `steps` steps.  Well
+    above the flat-interface value: the model's coexistence shifts with
+    curvature far more than the Kelvin estimate."""
+    T = frac * thermo.critical_temperature(a, B, R)
+    rg, rl, _ = thermo.maxwell(T, a, B, R, OMEGA)
+    p = dict(BASE, a=a, nx=n, ny=n, nz=n, sigma=sigma, thermal=0)
+    s = sim.Sim(**p)
+    s.init_fields(*W.droplet(n, n, n, radius, rl, guess, T, T, width=WIDTH))
+    s.step(steps)
+    rho = s.rho_u_T()[0]
+    s.close()
+    c = np.arange(n) - n / 2.0
+    r = np.sqrt(c[:, None, None] ** 2 + c[None, :, None] ** 2 + c[None, None, :] ** 2)
+    return round(float(rho[r > radius + 8.0].mean()), 4)
+
+
 def batch_cases(count, sigma):
     """Independent droplet lattices for the batched step: side L ~ U{24..96},
     T/Tc ~ U(BATCH_T_RANGE), R/L ~ U[0.15, 0.3], static or evaporating (vapour
@@ -210,6 +230,32 @@ def main():
             20000, f"bubble nucleation and departure (Sec. IV C), g = {g:g}: hydrophobic square of side 55 "
                    f"(phi = {phi_pho}, ~130 degrees) in a hydrophilic wall (phi = {phi_phi}, ~42 degrees), "
                    f"wall at 0.96 Tc, liquid to z = 200")
+
+    # Sec. IV B, droplet evaporation on a heated wall: 200 x 200 x 100, a
+    # hemisphere of radius 30 at the centre of the bottom wall, the Sec. IV A
+    # parameters (a = 1/49) with constant chi = 0.02, the wall at 0.87 T_c
+    # under the open top at T_sat = 0.86 T_c; `steps` is the isothermal settle
+    # that precedes heating.  Readings: the paper pins the contact line with
+    # the hysteresis window (0, 180) degrees of its Ref. [57] (not available);
+    # here a wettable disc of diameter 60 under the droplet (phi_in) in a
+    # non-wetting wall (phi) pins it on the disc's rim while the contact angle
+    # stays between the two angles; the vapour starts at the density a droplet
+    # of radius 30 holds in this model (droplet_vapour), not the flat-interface
+    # value it would otherwise take from the droplet.
+    phi_in_ccr, phi_out_ccr = 1.2, 0.8
+    th_in = contact_angle(phi_in_ccr, sig_a, a=A_IVA)
+    th_out = contact_angle(phi_out_ccr, sig_a, a=A_IVA)
+    rv_ccr = droplet_vapour(30.0, sig_a)
+    add("ccr_evaporation_200x200x100",
+        dict(bc_z=1, nx=200, ny=200, nz=100, kappa_mode=1, kappa=0.02, T_wall_patch=0.87 * TcA, T_wall=0.87 * TcA,
+             patch_radius=0.0, T_top=ca["T"], wet_mode=1, wet_phi=phi_out_ccr, wet_phi_in=phi_in_ccr, wet_drho=0.0,
+             wet_square=0.0, wet_disc=60.0),
+        dict(kind="droplet", radius=30.0, rho_l=ca["rho_l"], rho_g=rv_ccr, T_l=ca["T"], T_v=ca["T"], width=WIDTH,
+             center=[99.5, 99.5, -0.5]),
+        10000, f"droplet evaporation on a heated wall (Sec. IV B): hemisphere of radius 30, wall at 0.87 Tc, open "
+               f"top at 0.86 Tc, chi = 0.02; contact line pinned on the rim of a disc of diameter 60 (phi = "
+               f"{phi_in_ccr}, {th_in:.0f} degrees) in a wall of phi = {phi_out_ccr} ({th_out:.0f} degrees); vapour "
+               f"at {rv_ccr}, the density a droplet of radius 30 holds (flat interface: {ca['rho_g']:.4f})")
 
     wl["batch_256"] = batch_cases(256, sig_a)
 

@@ -23,7 +23,7 @@ def _param_fields(real):
         ("thermal", ctypes.c_int), ("bc_T_shell", ctypes.c_int), ("T_shell", real), ("thermal_bgk", ctypes.c_int),
         ("thermal_lattice", ctypes.c_int), ("divu_mode", ctypes.c_int), ("freeze_flow", ctypes.c_int),
         ("wet_mode", ctypes.c_int), ("wet_phi", real), ("wet_phi_in", real), ("wet_drho", real),
-        ("wet_square", real),
+        ("wet_square", real), ("wet_disc", real),
     ]
 
 
@@ -46,7 +46,7 @@ DEFAULTS = dict(nx=8, ny=8, nz=8, bc_z=0, a=2.0 / 49.0, b=2.0 / 21.0, R=1.0, ace
                 kappa_mode=0, kappa=0.2, vs_q=1.0, vs_pi=1.0, grav=(0.0, 0.0, 0.0),
                 T_wall_patch=0.0, T_wall=0.0, patch_radius=0.0, T_top=0.0, thermal=1, bc_T_shell=0, T_shell=0.0,
                 thermal_bgk=0, thermal_lattice=0, divu_mode=0, freeze_flow=0,
-                wet_mode=0, wet_phi=1.0, wet_phi_in=1.0, wet_drho=0.0, wet_square=0.0)
+                wet_mode=0, wet_phi=1.0, wet_phi_in=1.0, wet_drho=0.0, wet_square=0.0, wet_disc=0.0)
 
 _libs = {}
 

@@ -68,7 +68,7 @@ bool valid_params(const lbm_params *p) {
     if (p->wet_mode != LBM_WET_NEUTRAL && p->wet_mode != LBM_WET_VIRTUAL_DENSITY) return false;
     if (p->wet_mode == LBM_WET_VIRTUAL_DENSITY &&
         (p->bc_z == LBM_BC_PERIODIC || !(p->wet_phi > 0.0) || !(p->wet_phi_in > 0.0) || !(p->wet_drho >= 0.0) ||
-         !(p->wet_square >= 0.0)))
+         !(p->wet_square >= 0.0) || !(p->wet_disc >= 0.0)))
         return false;
     if (!(p->tau_e > 0.5) || !(p->tau_v > 0.5) || !(p->tau_q > 0.5) || !(p->tau_pi > 0.5)) return false;
     if (!(p->vs_q > 0.5) || !(p->vs_pi > 0.5)) return false;
@@ -174,6 +174,9 @@ Layout make_layout(const lbm_params *p) {
     L.total = off;
     return L;
 }
+
+// Squared radius of the wettability disc (0: none), for k_wall_density.
+double disc_r2(const lbm_params &p) { return 0.25 * p.wet_disc * p.wet_disc; }
 
 template <typename C>
 lbm::Phys<C> make_phys(const lbm_params *p) {
@@ -500,8 +503,8 @@ int step_once(lbm_handle *h) {
         // virtual density of the wall's solid layer from the state at time t
         const size_t nxy = (size_t)h->p.nx * h->p.ny;
         hipLaunchKernelGGL(lbm::k_wall_density<ST>, dim3((unsigned)((nxy + 255) / 256)), dim3(256), 0, h->stream,
-                           (const T *)h->pop(c), h->L.stride, h->p.nx, h->p.ny, make_phys<double>(&h->p), h->r_wall,
-                           h->status());
+                           (const T *)h->pop(c), h->L.stride, h->p.nx, h->p.ny, make_phys<double>(&h->p),
+                           disc_r2(h->p), h->r_wall, h->status());
     }
     int rc = h->p.bc_z != LBM_BC_PERIODIC ? launch_step_tile<ST, true>(h, A, nb) : launch_step_tile<ST, false>(h, A, nb);
     if (rc) return rc;
@@ -703,7 +706,7 @@ int lbm_get_rho_u_T(lbm_handle *h, double *rho, double *ux, double *uy, double *
         if (Pw.wet) {
             const size_t nxy = (size_t)h->p.nx * h->p.ny;
             hipLaunchKernelGGL(lbm::k_wall_density<ST>, dim3((unsigned)((nxy + 255) / 256)), dim3(256), 0, h->stream,
-                               pop, h->L.stride, h->p.nx, h->p.ny, Pw, h->r_wall, h->status());
+                               pop, h->L.stride, h->p.nx, h->p.ny, Pw, disc_r2(h->p), h->r_wall, h->status());
         }
         hipLaunchKernelGGL(lbm::k_macro<ST>, dim3(nb), dim3(256), 0, h->stream, pop, h->L.stride, nn, P, st);
         hipLaunchKernelGGL(lbm::k_velocity<ST>, dim3(nb), dim3(256), 0, h->stream, pop, h->L.stride, h->p.nx, h->p.ny,

@@ -1647,11 +1647,13 @@ __global__ void __launch_bounds__(256) k_init(const double *__restrict__ stage, 
 // and drho those of the centred square or of the rest of the wall, and
 // psi_w of Eq. (8) at rho_w and the temperature of the fluid node above it.
 // Evaluated in FP64 from the state at time t (before the step, and before
-// the readout); sets status bit 1 where rho_w <= 0 or psi_w^2 < 0.
+// the readout); sets status bit 1 where rho_w <= 0 or psi_w^2 < 0.  The
+// patch (phi_in, drho) is the square of side P.wet_square and the disc of
+// squared radius disc_r2 centred at (cx, cy).
 template <typename ST>
 __global__ void __launch_bounds__(256) k_wall_density(const typename ST::T *__restrict__ pop, size_t st, int nx,
-                                                      int ny, Phys<double> P, double *__restrict__ wall,
-                                                      unsigned *__restrict__ status) {
+                                                      int ny, Phys<double> P, double disc_r2,
+                                                      double *__restrict__ wall, unsigned *__restrict__ status) {
     const size_t nxy = (size_t)nx * ny;
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nxy) return;
@@ -1678,9 +1680,10 @@ __global__ void __launch_bounds__(256) k_wall_density(const typename ST::T *__re
     for (int a = 0; a < QT; ++a) gl[a] = v.e(19 + a, i);
     const double T = v.ref(1, i) + sum_T<QT>(gl);
     const double rho_ave = num / den;
-    const double h = 0.5 * P.wet_square;
-    const bool in_square = P.wet_square > 0.0 && fabs(x - P.cx) <= h && fabs(y - P.cy) <= h;
-    const double rw = in_square ? P.wet_phi_in * rho_ave - P.wet_drho : P.wet_phi * rho_ave;
+    const double h = 0.5 * P.wet_square, dx = x - P.cx, dy = y - P.cy;
+    const bool in_patch = (P.wet_square > 0.0 && fabs(dx) <= h && fabs(dy) <= h) ||
+                          (disc_r2 > 0.0 && dx * dx + dy * dy <= disc_r2);
+    const double rw = in_patch ? P.wet_phi_in * rho_ave - P.wet_drho : P.wet_phi * rho_ave;
     const double p2 = psi_squared(P, rw, T);
     if (!(rw > 0.0) || !(p2 >= 0.0)) atomicOr(status, 1u);
     wall[i] = rw;

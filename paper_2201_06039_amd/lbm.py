@@ -38,7 +38,7 @@ class LbmParams(ctypes.Structure):
         ("bc_T_shell", ctypes.c_int), ("T_shell", ctypes.c_double), ("thermal_bgk", ctypes.c_int),
         ("thermal_lattice", ctypes.c_int), ("divu_mode", ctypes.c_int),
         ("wet_mode", ctypes.c_int), ("wet_phi", ctypes.c_double), ("wet_phi_in", ctypes.c_double),
-        ("wet_drho", ctypes.c_double), ("wet_square", ctypes.c_double),
+        ("wet_drho", ctypes.c_double), ("wet_square", ctypes.c_double), ("wet_disc", ctypes.c_double),
     ]
 
 
@@ -138,6 +138,7 @@ def make_params(params: dict, storage="f32") -> LbmParams:
     src.setdefault("wet_phi_in", 1.0)
     src.setdefault("wet_drho", 0.0)
     src.setdefault("wet_square", 0.0)
+    src.setdefault("wet_disc", 0.0)
     for n in names:
         if n not in src:
             raise KeyError(f"missing parameter {n!r}")

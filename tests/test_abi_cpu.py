@@ -36,6 +36,28 @@ def test_every_declared_symbol_is_exported(lib):
     assert sorted(lbm.EXPORTS) == declared_functions()
 
 
+def test_params_struct_matches_the_header(tmp_path):
+    """The binding's lbm_params has the C struct's size and every field at
+    its C offset (include/lbm.h compiled with the host C compiler)."""
+    import shutil
+    import subprocess
+    from paper_2201_06039_amd import lbm
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    fields = [f[0] for f in lbm.LbmParams._fields_]
+    src = ('#include <stdio.h>\n#include <stddef.h>\n#include "lbm.h"\nint main(void) {\n'
+           '    printf("%zu\\n", sizeof(lbm_params));\n' +
+           "".join(f'    printf("%zu\\n", offsetof(lbm_params, {f}));\n' for f in fields) + "    return 0;\n}\n")
+    (tmp_path / "offsets.c").write_text(src)
+    exe = str(tmp_path / "offsets")
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), "-o", exe, str(tmp_path / "offsets.c")], check=True)
+    out = [int(v) for v in subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()]
+    assert out[0] == ctypes.sizeof(lbm.LbmParams)
+    for f, off in zip(fields, out[1:]):
+        assert getattr(lbm.LbmParams, f).offset == off, f
+
+
 def test_arena_bytes_and_validation(lib):
     from paper_2201_06039_amd import lbm, workloads as W
     p = W.load("evaporation_128")["params"]

@@ -355,10 +355,11 @@ def test_fd_divergence_launch_shapes(storage):
 # hydrophilic wall, Sec. IV C's pattern) under the open top and in the closed
 # box of Sec. IV C (bounce-back at the top too), with gravity and the heated
 # wall.
-def _wet_case(closed):
+def _wet_case(closed, patch="square"):
     from oracle import thermo
     Tc = thermo.critical_temperature(2.0 / 49.0, 2.0 / 21.0, 1.0)
-    w = workload("pool_boiling_32x32x48", wet_mode=1, wet_phi=1.3, wet_phi_in=0.8, wet_square=13.0,
+    shape = dict(wet_square=13.0) if patch == "square" else dict(wet_disc=15.0)
+    w = workload("pool_boiling_32x32x48", wet_mode=1, wet_phi=1.3, wet_phi_in=0.8, **shape,
                  T_wall_patch=0.96 * Tc, T_wall=0.93 * Tc, patch_radius=9.0)
     if closed:
         w["params"].update(bc_z=2, nz=40)
@@ -366,12 +367,13 @@ def _wet_case(closed):
     return w
 
 
+@pytest.mark.parametrize("patch", ["square", "disc"])
 @pytest.mark.parametrize("closed", [False, True], ids=["open_top", "closed_box"])
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
-def test_wetting_walls_against_oracle(storage, closed):
-    w = _wet_case(closed)
+def test_wetting_walls_against_oracle(storage, closed, patch):
+    w = _wet_case(closed, patch)
     steps = 60
-    _say(f"wetting walls closed={closed} {storage} steps={steps}")
+    _say(f"wetting walls closed={closed} patch={patch} {storage} steps={steps}")
     ref = run_oracle(w, steps)
     e = errors(run_gpu(w, steps, storage, chunks=[1, 29, 30]), ref)
     _say(f"  errors {e}")
@@ -379,6 +381,27 @@ def test_wetting_walls_against_oracle(storage, closed):
         _check(e, FP64_TOL)
     elif storage == "f32":
         check_fp32(f"wetting/{'closed' if closed else 'open'}/{steps}", w, steps, e, ref)
+    else:
+        tol = DEV_TOL["f16"]
+        assert e["rho"] <= tol and e["T"] <= tol and e["u_l2"] <= 20 * tol, e
+
+
+# The droplet on the heated wall of Sec. IV B, scaled down: the open top at
+# T_sat, the wall at 0.87 T_c, constant chi = 0.02, a = 1/49, the contact
+# line on the rim of a wettable disc in a non-wetting wall.
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_ccr_case_against_oracle(storage):
+    w = workload("ccr_evaporation_200x200x100", nx=40, ny=36, nz=24, wet_disc=16.0, radius=8.0,
+                 center=[19.5, 17.5, -0.5])
+    steps = 60
+    _say(f"ccr case {storage} steps={steps}")
+    ref = run_oracle(w, steps)
+    e = errors(run_gpu(w, steps, storage, chunks=[1, 29, 30]), ref)
+    _say(f"  errors {e}")
+    if storage == "f64":
+        _check(e, FP64_TOL)
+    elif storage == "f32":
+        check_fp32(f"ccr/{steps}", w, steps, e, ref)
     else:
         tol = DEV_TOL["f16"]
         assert e["rho"] <= tol and e["T"] <= tol and e["u_l2"] <= 20 * tol, e

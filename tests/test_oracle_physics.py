@@ -873,6 +873,40 @@ def _sessile(oracle_lib, phi, steps=6000, nx=120, nz=60, r0=25.0, square=0.0, ph
     return wetting.contact_angle_2d(rho[:, 0, :], 0.5 * (rl + rg))
 
 
+def test_wettability_patch_geometry(oracle_lib):
+    """The virtual-density patch (phi_in) is the centred square of side
+    wet_square, the centred disc of diameter wet_disc, or both.  On a uniform
+    fluid at rest only patch nodes differ from their fluid neighbours, and the
+    force of Eq. (7) reaches a node of the first fluid layer from the five
+    solid nodes below it (e_z = -1), so the nodes whose readout u_z (which
+    holds F/2 at t = 0) is not zero are exactly the patch dilated by that
+    cross, and no other layer moves.  Checked against a brute-force mask for
+    discs of odd and even diameter on a grid with a half-integer centre in y,
+    a square, and a disc with a square."""
+    T = 0.0627
+    nx, ny, nz = 21, 23, 6
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    cx, cy = 0.5 * (nx - 1), 0.5 * (ny - 1)
+    for disc, square in ((9.0, 0.0), (8.0, 0.0), (0.0, 5.0), (9.0, 5.0)):
+        s = oracle_lib.Sim(nx=nx, ny=ny, nz=nz, bc_z=2, sigma=0.11, kappa_mode=1, kappa=0.08, T_wall_patch=T,
+                           T_wall=T, T_top=T, thermal=0, wet_mode=1, wet_phi=1.0, wet_phi_in=1.2,
+                           wet_disc=disc, wet_square=square)
+        ones = np.ones((nz, ny, nx))
+        s.init_fields(6.0 * ones, 0 * ones, 0 * ones, 0 * ones, T * ones)
+        uz = s.rho_u_T()[3]
+        s.close()
+        inside = np.zeros((ny, nx), dtype=bool)
+        if disc:
+            inside |= (xx - cx) ** 2 + (yy - cy) ** 2 <= (0.5 * disc) ** 2
+        if square:
+            inside |= (np.abs(xx - cx) <= 0.5 * square) & (np.abs(yy - cy) <= 0.5 * square)
+        cross = inside.copy()
+        for ax, sh in ((0, 1), (0, -1), (1, 1), (1, -1)):
+            cross |= np.roll(inside, sh, ax)
+        assert np.array_equal(np.abs(uz[0]) > 1e-12, cross), (disc, square)
+        assert np.abs(uz[1:]).max() == 0.0
+
+
 @pytest.mark.slow
 def test_virtual_density_contact_angles(oracle_lib):
     """phi = 1 is close to a neutral wall (90 degrees; the scheme's rho_ave
