@@ -351,6 +351,8 @@ int hip_status(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EHIP; }
 // planes; the z halo of a chunk is read twice, so chunks are kept long
 // (64 planes: 2-3% faster than 32 at 512^3 and on the pool) unless the grid
 // would then give fewer workgroups than the 256 compute units.
+bool buffer_path(const Layout &L);
+
 void set_default_launch(lbm_handle *h) {
     const int nx = h->p.nx, ny = h->p.ny, nz = h->p.nz;
     const bool half = h->L.es == 2;
@@ -376,12 +378,13 @@ void set_default_launch(lbm_handle *h) {
         h->tile_y = nx > 32 ? 4 : 8;
     }
     const long tiles = (long)((nx + h->tile_x - 1) / h->tile_x) * ((ny + h->tile_y - 1) / h->tile_y);
-    // About one workgroup per compute unit.  16-bit storage takes the longest
-    // chunks that allows (measured against chunks of 64 planes: 512^3 -2%,
-    // the 256x256x384 wall grid -9%); the 4- and 8-byte formats stop at 64
-    // planes (512^3 FP32: 6.46 ms with 64, 6.63 ms with 128).
+    // About one workgroup per compute unit, with the longest chunks that
+    // allows (measured against chunks of 64 planes: 512^3 FP16 -2%, the
+    // 256x256x384 wall grid FP16 -9%, FP32 -10%), except for grids on the
+    // plain-pointer path in 4- or 8-byte storage, which stop at 64 planes
+    // (512^3 FP32: 6.46 ms with 64, 6.63 ms with 256, 6.67 ms with 512).
     long cz = (long)nz * tiles / 256;
-    if (cz > 64 && !half) cz = 64;
+    if (cz > 64 && !half && !buffer_path(h->L)) cz = 64;
     if (cz < 4) cz = 4;
     if (cz > nz) cz = nz;
     h->chunk_z = (int)cz;
