@@ -407,6 +407,45 @@ def test_ccr_case_against_oracle(storage):
         assert e["rho"] <= tol and e["T"] <= tol and e["u_l2"] <= 20 * tol, e
 
 
+@pytest.mark.parametrize("storage", ["f64", "f16"])
+def test_ccr_settle_then_heat_against_oracle(storage):
+    """The heated-wall study's two phases: steps with the temperature lattice
+    held (thermal = 0), then the checkpoint continued by a lattice with
+    thermal = 1 -- on both sides, against the oracle doing the same."""
+    from oracle import sim
+    from paper_2201_06039_amd import lbm, workloads as W
+    w = workload("ccr_evaporation_200x200x100", nx=40, ny=36, nz=24, wet_disc=16.0, radius=8.0,
+                 center=[19.5, 17.5, -0.5])
+    held, heated = 20, 40
+    _say(f"ccr settle then heat {storage}: {held} + {heated} steps")
+    o = sim.Sim(**dict(w["params"], thermal=0))
+    o.init_fields(*W.fields(w))
+    o.step(held)
+    st = o.state()
+    o.close()
+    o = sim.Sim(**w["params"])
+    o.set_state(st["f"], st["g"], st["phi_prev"], st["rho_ave"])
+    o.step(heated)
+    ref = o.rho_u_T()
+    o.close()
+    lat = lbm.Lattice(dict(w["params"], thermal=0), storage=storage, device="cuda:0")
+    lat.init_fields(*W.fields(w))
+    lat.step(held)
+    blob = lat.get_state()
+    lat.close()
+    lat = lbm.Lattice(w["params"], storage=storage, device="cuda:0")
+    lat.set_state(blob)
+    lat.step(heated)
+    e = errors(lat.rho_u_T(), ref)
+    lat.close()
+    _say(f"  errors {e}")
+    if storage == "f64":
+        _check(e, FP64_TOL)
+    else:
+        tol = DEV_TOL["f16"]
+        assert e["rho"] <= tol and e["T"] <= tol and e["u_l2"] <= 20 * tol, e
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_wetting_walls_launch_shape_bitwise(storage):
     """The solid layer's virtual density reaches every tile and halo node
