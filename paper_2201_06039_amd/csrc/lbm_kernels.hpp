@@ -733,10 +733,10 @@ __device__ __forceinline__ void step_tile(const StepArgs<ST> &A, int logical, in
     // in flight, which would wait for every load and store of the wave.
     // Measured: FP32 512^3 7.66 -> 6.47 ms, pool grid -5%; 16-bit periodic
     // grids with 64x8 tiles -2% (512^3, against 128x4 without) and -3%
-    // (128^3), the FP16 batch -3%; 16-bit walls +4% (not used there), and
-    // the D3Q19 temperature lattice keeps its words in registers.
-    constexpr bool STASH =
-        paired_layout<E>() && (sizeof(E) == 4 || FIT || (!WALLS && ST::kQT == 7));
+    // (128^3), the FP16 batch -3%; 16-bit walls +4% and the D3Q19
+    // temperature lattice in FP32 +15% (128^3), so those keep their words in
+    // registers.
+    constexpr bool STASH = paired_layout<E>() && ST::kQT == 7 && (sizeof(E) == 4 || FIT || !WALLS);
     // The float constants of the model are read by vector instructions in
     // every iteration; held in scalar registers they exceed the scalar
     // register file and are spilled to vector lanes, costing one read per use.
