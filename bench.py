@@ -540,8 +540,8 @@ def main():
                     help="only run the bubble nucleation and departure test of Sec. IV C at five gravities "
                          "(about 3 minutes) and print its JSON")
     ap.add_argument("--ccr", action="store_true",
-                    help="only run the evaporation of a pinned droplet on the heated wall of Sec. IV B (FP64, FP32 "
-                         "and FP16 storage, about 9 minutes) and print its JSON")
+                    help="only run the evaporation of a pinned droplet on the heated wall of Sec. IV B (every "
+                         "storage format, about 14 minutes) and print its JSON")
     ap.add_argument("--workloads", default="evaporation_128,pool_boiling_256x256x384",
                     help="comma-separated workloads timed in the other-workload leg")
     ap.add_argument("--divu", default="local", choices=["local", "fd"],
@@ -572,7 +572,7 @@ def main():
         return
 
     if args.ccr:
-        runs = [ccr_evaporation(lbm, W, storage=st) for st in ("f64", "f32", "f16")]
+        runs = [ccr_evaporation(lbm, W, storage=st) for st in ("f64", "f32", "f32dev", "f16", "bf16")]
         ref = {s["t"]: s for s in runs[0]["samples"]}
         for r in runs[1:]:
             common = [s for s in r["samples"] if s["t"] in ref]
