@@ -314,6 +314,11 @@ int lbm_batch_get_launch(const lbm_batch *b, int *tile_x, int *tile_y, int *chun
  * tiles).  EINVAL for a bad index or NULL output. */
 int lbm_batch_case_tile(const lbm_batch *b, int c, int *tile_x, int *tile_y, int *threads);
 
+/* The fitted tile a batch gives a lattice with these parameters (launch tile
+ * 0 x 0, above), computed on the host without a device: its workgroups have
+ * 512 threads.  EINVAL for invalid parameters, FP64 storage or NULL output. */
+int lbm_fitted_tile(const lbm_params *p, int *tile_x, int *tile_y);
+
 /* Autotuner: times `steps` launches of each candidate launch shape (every
  * supported tile and fitted tiles, chunks of 8, 16, 32, 64 and 128 planes --
  * the nodes each thread updates --, one and two persistent

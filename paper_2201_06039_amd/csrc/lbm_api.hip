@@ -1354,6 +1354,14 @@ int lbm_batch_case_tile(const lbm_batch *b, int c, int *tile_x, int *tile_y, int
     *threads = b->tile_x ? t.tx * t.ty : kFitThreads;
     return LBM_OK;
 }
+int lbm_fitted_tile(const lbm_params *p, int *tile_x, int *tile_y) {
+    if (!p || !tile_x || !tile_y || !valid_params(p) || p->storage == LBM_STORE_F64) return LBM_EINVAL;
+    const TileShape t = fitted_tile(*p);
+    *tile_x = t.tx;
+    *tile_y = t.ty;
+    return LBM_OK;
+}
+
 int lbm_batch_get_launch(const lbm_batch *b, int *tile_x, int *tile_y, int *chunk_z, int *workgroups, int *items) {
     if (!b || !tile_x || !tile_y || !chunk_z || !workgroups || !items) return LBM_EINVAL;
     *tile_x = b->tile_x;

@@ -49,7 +49,7 @@ EXPORTS = ("lbm_arena_bytes", "lbm_create", "lbm_init_fields", "lbm_step", "lbm_
            "lbm_launches_per_step", "lbm_destroy", "lbm_strerror",
            "lbm_batch_arena_bytes", "lbm_batch_create", "lbm_batch_init_case", "lbm_batch_step",
            "lbm_batch_get_rho_u_T", "lbm_batch_reduce", "lbm_batch_set_launch", "lbm_batch_get_launch",
-           "lbm_batch_case_tile", "lbm_batch_autotune", "lbm_batch_destroy", "lbm_copy_probe")
+           "lbm_batch_case_tile", "lbm_fitted_tile", "lbm_batch_autotune", "lbm_batch_destroy", "lbm_copy_probe")
 
 _lib = None
 
@@ -99,6 +99,7 @@ def load_library():
     L.lbm_batch_set_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.lbm_batch_get_launch.argtypes = [vp, ip, ip, ip, ip, ip]
     L.lbm_batch_case_tile.argtypes = [vp, ctypes.c_int, ip, ip, ip]
+    L.lbm_fitted_tile.argtypes = [ctypes.POINTER(LbmParams), ip, ip]
     L.lbm_batch_autotune.argtypes = [vp, ctypes.c_int, dp]
     L.lbm_batch_destroy.argtypes = [vp]
     L.lbm_batch_destroy.restype = None
@@ -108,6 +109,7 @@ def load_library():
                  "lbm_set_state", "lbm_set_launch", "lbm_get_launch", "lbm_launches_per_step",
                  "lbm_batch_create", "lbm_batch_init_case", "lbm_batch_step", "lbm_batch_get_rho_u_T",
                  "lbm_batch_reduce", "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_case_tile",
+                 "lbm_fitted_tile",
                  "lbm_batch_autotune", "lbm_copy_probe"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -154,6 +156,15 @@ def make_params(params: dict, storage="f32") -> LbmParams:
 
 def arena_bytes(params: dict, storage="f32") -> int:
     return load_library().lbm_arena_bytes(ctypes.byref(make_params(params, storage)))
+
+
+def fitted_tile(params: dict, storage="f16"):
+    """(tile_x, tile_y) of the fitted tile a batch gives this lattice."""
+    tx, ty = ctypes.c_int(), ctypes.c_int()
+    rc = load_library().lbm_fitted_tile(ctypes.byref(make_params(params, storage)), ctypes.byref(tx), ctypes.byref(ty))
+    if rc != OK:
+        raise LbmError("lbm_fitted_tile", rc)
+    return tx.value, ty.value
 
 
 def _params_array(cases, storage):

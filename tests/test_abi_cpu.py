@@ -58,6 +58,52 @@ def test_params_struct_matches_the_header(tmp_path):
         assert getattr(lbm.LbmParams, f).offset == off, f
 
 
+def _fitted_rule(nx, ny):
+    """The selection the batch documents, written out: of the tiles with
+    256..512 nodes whose extended tile fits 700 LDS nodes and that are exactly
+    nx wide (nx <= 128) or 4k wide from 64 to below nx (and 128 at most), the
+    one with the fewest idle slots of 512-thread workgroups; within 2% of it
+    the smaller halo (two rows for whole-row tiles), then the wider tile."""
+    import math
+    widths = ([nx] if 2 <= nx <= 128 else []) + [t for t in range(64, 129, 4) if t < nx]
+    best, be, bh = (32, 16), -1.0, 1 << 30
+    for tx in widths:
+        for ty in range(1, 257):
+            if not 256 <= tx * ty <= 512 or (tx + 2) * (ty + 2) > 700:
+                continue
+            e = nx * ny / (math.ceil(nx / tx) * math.ceil(ny / ty) * 512)
+            halo = 2 * tx if tx == nx else 2 * (tx + ty) + 4
+            if e > be + 0.02 or (e > be - 0.02 and (halo < bh or (halo == bh and tx > best[0]))):
+                best, be, bh = (tx, ty), max(be, e), halo
+    return best
+
+
+def test_fitted_tiles_on_the_host(lib):
+    """The fitted tile of every lattice of the 256-lattice batch, computed on
+    the host (no device): it follows the documented rule, and the batch's
+    thread slots hold nodes with the efficiency the batch reports (0.890)."""
+    import math
+    from paper_2201_06039_amd import lbm, workloads as W
+    cases = W.load("batch_256")["cases"]
+    nodes = slots = 0
+    for c in cases:
+        p = c["params"]
+        nx, ny, nz = p["nx"], p["ny"], p["nz"]
+        tx, ty = lbm.fitted_tile(p, "f16")
+        assert 256 <= tx * ty <= 512 and (tx + 2) * (ty + 2) <= 700, (nx, tx, ty)
+        assert tx == nx or (tx % 4 == 0 and 64 <= tx < nx), (nx, tx)
+        assert (tx, ty) == _fitted_rule(nx, ny), (nx, ny, tx, ty)
+        nodes += nx * ny * nz
+        slots += math.ceil(nx / tx) * math.ceil(ny / ty) * 512 * nz
+    assert abs(nodes / slots - 0.8904) < 5e-4
+    # other sizes: odd, narrow, wider than 128, ragged
+    for nx, ny in ((17, 33), (85, 20), (150, 9), (200, 200), (2, 300)):
+        p = dict(cases[0]["params"], nx=nx, ny=ny, nz=8)
+        assert lbm.fitted_tile(p, "f16") == _fitted_rule(nx, ny), (nx, ny)
+    with pytest.raises(lbm.LbmError):
+        lbm.fitted_tile(cases[0]["params"], "f64")
+
+
 def test_arena_bytes_and_validation(lib):
     from paper_2201_06039_amd import lbm, workloads as W
     p = W.load("evaporation_128")["params"]
