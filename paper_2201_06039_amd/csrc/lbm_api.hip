@@ -378,15 +378,29 @@ void set_default_launch(lbm_handle *h) {
         h->tile_y = nx > 32 ? 4 : 8;
     }
     const long tiles = (long)((nx + h->tile_x - 1) / h->tile_x) * ((ny + h->tile_y - 1) / h->tile_y);
-    // About one workgroup per compute unit, with the longest chunks that
-    // allows (measured against chunks of 64 planes: 512^3 FP16 -2%, the
-    // 256x256x384 wall grid FP16 -9%, FP32 -10%), except for grids on the
-    // plain-pointer path in 4- or 8-byte storage, which stop at 64 planes
-    // (512^3 FP32: 6.46 ms with 64, 6.63 ms with 256, 6.67 ms with 512).
-    long cz = (long)nz * tiles / 256;
-    if (cz > 64 && !half && !buffer_path(h->L)) cz = 64;
-    if (cz < 4) cz = 4;
-    if (cz > nz) cz = nz;
+    // Chunk depth: the one that minimises the waves of workgroups times the
+    // planes each workgroup marches (plus 3 for the pipeline's start), with
+    // 256 workgroups of 512 threads (or 512 of 256) in flight on the 256
+    // compute units.  This takes the longest chunks at about one workgroup
+    // per compute unit where the tiles divide the grid well (512^3: whole
+    // 512-plane columns, -2% against chunks of 64 planes; the 256x256x384
+    // wall grid: 192 planes, -9% FP16, -10% FP32) and avoids a partial
+    // last wave where they do not (200x200x100: 20 planes, 500 workgroups,
+    // rather than 39 planes and 300).  Grids on the plain-pointer path in 4-
+    // or 8-byte storage stop at 64 planes (512^3 FP32: 6.46 ms with 64, 6.63
+    // ms with 256, 6.67 ms with 512).
+    const long resident = 256L * (h->tile_x * h->tile_y >= 512 ? 1 : 512 / (h->tile_x * h->tile_y));
+    const long cap = (!half && !buffer_path(h->L)) ? (nz < 64 ? nz : 64) : nz;
+    long cz = 1;
+    double best = 1e300;
+    for (long c = 1; c <= cap; ++c) {
+        const long wg = tiles * ((nz + c - 1) / c);
+        const double cost = (double)((wg + resident - 1) / resident) * (double)(c + 3);
+        if (cost <= best) {
+            best = cost;
+            cz = c;
+        }
+    }
     h->chunk_z = (int)cz;
 }
 
