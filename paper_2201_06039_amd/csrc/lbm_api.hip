@@ -380,8 +380,9 @@ void set_default_launch(lbm_handle *h) {
     const long tiles = (long)((nx + h->tile_x - 1) / h->tile_x) * ((ny + h->tile_y - 1) / h->tile_y);
     // Chunk depth: the one that minimises the waves of workgroups times the
     // planes each workgroup marches (plus 3 for the pipeline's start), with
-    // 256 workgroups of 512 threads (or 512 of 256) in flight on the 256
-    // compute units.  This takes the longest chunks at about one workgroup
+    // as many workgroups in flight as the 256 compute units hold: one of 512
+    // threads each, or two of 256 (one where a 256-thread step needs more
+    // than 256 registers a lane: the D3Q19 temperature lattice, FP64).  This takes the longest chunks at about one workgroup
     // per compute unit where the tiles divide the grid well (512^3: whole
     // 512-plane columns, -2% against chunks of 64 planes; the 256x256x384
     // wall grid: 192 planes, -9% FP16, -10% FP32) and avoids a partial
@@ -389,7 +390,8 @@ void set_default_launch(lbm_handle *h) {
     // rather than 39 planes and 300).  Grids on the plain-pointer path in 4-
     // or 8-byte storage stop at 64 planes (512^3 FP32: 6.46 ms with 64, 6.63
     // ms with 256, 6.67 ms with 512).
-    const long resident = 256L * (h->tile_x * h->tile_y >= 512 ? 1 : 512 / (h->tile_x * h->tile_y));
+    const bool one_per_cu = h->tile_x * h->tile_y >= 512 || h->L.qt == 19 || h->p.storage == LBM_STORE_F64;
+    const long resident = one_per_cu ? 256L : 512L;
     const long cap = (!half && !buffer_path(h->L)) ? (nz < 64 ? nz : 64) : nz;
     long cz = 1;
     double best = 1e300;
