@@ -538,10 +538,10 @@ def main():
                          "and print its JSON")
     ap.add_argument("--nucleation", action="store_true",
                     help="only run the bubble nucleation and departure test of Sec. IV C at five gravities "
-                         "(about 3 minutes) and print its JSON")
+                         "(a few minutes) and print its JSON")
     ap.add_argument("--ccr", action="store_true",
                     help="only run the evaporation of a pinned droplet on the heated wall of Sec. IV B (every "
-                         "storage format, about 14 minutes) and print its JSON")
+                         "storage format, several minutes) and print its JSON")
     ap.add_argument("--workloads", default="evaporation_128,pool_boiling_256x256x384",
                     help="comma-separated workloads timed in the other-workload leg")
     ap.add_argument("--divu", default="local", choices=["local", "fd"],
